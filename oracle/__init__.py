@@ -1,0 +1,162 @@
+"""ctypes wrapper of the sequential CPU oracle (``ndo.c``).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU baseline of
+the benchmark may import this package; the product library and its Python
+binding never do. It shares no code with the GPU path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ndo.c")
+_LIB = os.path.join(_HERE, "libndo.so")
+
+NDO_OK = 0
+NDO_E_INVALID_ARG = 1
+NDO_E_BAD_GRAPH = 2
+NDO_E_OOM = 3
+NONE = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+class _Result(C.Structure):
+    _fields_ = [
+        ("n", C.c_uint32), ("r", C.c_uint32), ("s", C.c_uint32),
+        ("n_r", C.c_uint64), ("n_s", C.c_uint64),
+        ("rcliques", C.POINTER(C.c_uint32)),
+        ("count", C.POINTER(C.c_uint64)),
+        ("coreness", C.POINTER(C.c_uint64)),
+        ("peel_order", C.POINTER(C.c_uint64)),
+        ("k", C.c_uint64),
+        ("n_int", C.c_uint64),
+        ("parent", C.POINTER(C.c_uint64)),
+        ("level", C.POINTER(C.c_uint64)),
+        ("t_count", C.c_double), ("t_peel", C.c_double), ("t_tree", C.c_double),
+    ]
+
+
+def build(force: bool = False) -> str:
+    """Compile ``libndo.so`` with gcc (portable flags, single-threaded)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O3", "-std=c11", "-Wall", "-fPIC", "-shared",
+                               _SRC, "-o", tmp])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = C.CDLL(_LIB)
+        u64p = C.POINTER(C.c_uint64)
+        u32p = C.POINTER(C.c_uint32)
+        lib.ndo_validate_csr.argtypes = [C.c_uint32, u64p, u32p]
+        lib.ndo_validate_csr.restype = C.c_int
+        lib.ndo_decompose.argtypes = [C.c_uint32, u64p, u32p, C.c_uint32, C.c_uint32,
+                                      C.POINTER(_Result)]
+        lib.ndo_decompose.restype = C.c_int
+        lib.ndo_count.argtypes = lib.ndo_decompose.argtypes
+        lib.ndo_count.restype = C.c_int
+        lib.ndo_free.argtypes = [C.POINTER(_Result)]
+        lib.ndo_free.restype = None
+        _lib = lib
+    return _lib
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int):
+        super().__init__(f"oracle error code {code}")
+        self.code = code
+
+
+@dataclass
+class Decomposition:
+    n: int
+    r: int
+    s: int
+    n_r: int
+    n_s: int
+    rcliques: np.ndarray      # uint32 [n_r, r]
+    count: np.ndarray         # uint64 [n_r]
+    coreness: np.ndarray | None = None    # uint64 [n_r]
+    peel_order: np.ndarray | None = None  # uint64 [n_r]
+    k: int = 0
+    n_int: int = 0
+    parent: np.ndarray | None = None      # uint64 [n_r + n_int]
+    level: np.ndarray | None = None       # uint64 [n_int]
+    t_count: float = 0.0
+    t_peel: float = 0.0
+    t_tree: float = 0.0
+
+
+def _arr(ptr, n, dtype):
+    if n == 0:
+        return np.zeros(0, dtype=dtype)
+    return np.ctypeslib.as_array(ptr, shape=(n,)).astype(dtype, copy=True)
+
+
+def _csr_args(csr):
+    rp = np.ascontiguousarray(csr.row_ptr, dtype=np.uint64)
+    col = np.ascontiguousarray(csr.col, dtype=np.uint32)
+    if col.size == 0:
+        col = np.zeros(1, dtype=np.uint32)
+    return rp, col
+
+
+def validate(csr) -> int:
+    lib = _load()
+    rp, col = _csr_args(csr)
+    return lib.ndo_validate_csr(csr.n, rp.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                col.ctypes.data_as(C.POINTER(C.c_uint32)))
+
+
+def _run(fn_name: str, csr, r: int, s: int, full: bool) -> Decomposition:
+    lib = _load()
+    rp, col = _csr_args(csr)
+    res = _Result()
+    st = getattr(lib, fn_name)(csr.n, rp.ctypes.data_as(C.POINTER(C.c_uint64)),
+                               col.ctypes.data_as(C.POINTER(C.c_uint32)), r, s,
+                               C.byref(res))
+    if st != NDO_OK:
+        raise OracleError(st)
+    try:
+        n_r = int(res.n_r)
+        d = Decomposition(
+            n=int(res.n), r=int(res.r), s=int(res.s), n_r=n_r, n_s=int(res.n_s),
+            rcliques=_arr(res.rcliques, n_r * r, np.uint32).reshape(n_r, r),
+            count=_arr(res.count, n_r, np.uint64),
+            t_count=float(res.t_count))
+        if full:
+            n_int = int(res.n_int)
+            d.coreness = _arr(res.coreness, n_r, np.uint64)
+            d.peel_order = _arr(res.peel_order, n_r, np.uint64)
+            d.k = int(res.k)
+            d.n_int = n_int
+            d.parent = _arr(res.parent, n_r + n_int, np.uint64)
+            d.level = _arr(res.level, n_int, np.uint64)
+            d.t_peel = float(res.t_peel)
+            d.t_tree = float(res.t_tree)
+        return d
+    finally:
+        lib.ndo_free(C.byref(res))
+
+
+def decompose(csr, r: int, s: int) -> Decomposition:
+    """Full oracle: r-cliques, counts, coreness, canonical tree."""
+    return _run("ndo_decompose", csr, r, s, True)
+
+
+def count(csr, r: int, s: int) -> Decomposition:
+    """Only r-clique listing and per-r-clique s-clique counts."""
+    return _run("ndo_count", csr, r, s, False)

@@ -1,0 +1,676 @@
+/*
+ * ndo.c -- plain sequential CPU oracle for exact (r,s) nucleus decomposition
+ * and its hierarchy. TEST INFRASTRUCTURE ONLY (see ndo.h): the product
+ * library never includes, links or calls this file.
+ *
+ * Deliberately simple: every step follows a definition from the paper with
+ * plain loops, sorted-array binary searches and no parallelism, blocking or
+ * fusion. Speed is not a goal.
+ *
+ * Steps (arXiv 2306.08623):
+ *   O1  list r-cliques as ascending tuples in lexicographic order
+ *       (the canonical r-clique id is the index in this order);
+ *   O2  list every s-clique once and add one to the count of each of its
+ *       C(s,r) r-cliques (Section 3: s-clique degree);
+ *   O3  sequential minimum-degree peel (Section 6, proof of Lemma 1):
+ *       core number = running maximum of the minimum current degree;
+ *   O4  hierarchy from the definition (Section 5, Algorithm 1 semantics;
+ *       Section 7.4 practical form): descending levels, one union-find;
+ *   O5  canonical numbering of the internal nodes by (level, min leaf).
+ */
+#define _POSIX_C_SOURCE 199309L
+#include "ndo.h"
+
+#include <stdlib.h>
+#include <string.h>
+#include <time.h>
+
+#define MAXS 7
+#define NONE UINT64_MAX
+
+typedef struct {
+  uint32_t n;
+  const uint64_t *rp;
+  const uint32_t *col;
+  uint64_t maxdeg;
+} graph;
+
+static double now_s(void) {
+  struct timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+/* ---- growable arrays ---------------------------------------------------- */
+
+typedef struct { uint32_t *a; uint64_t n, cap; int oom; } vec32;
+typedef struct { uint64_t *a; uint64_t n, cap; int oom; } vec64;
+
+static void v32_push(vec32 *v, uint32_t x) {
+  if (v->oom) return;
+  if (v->n == v->cap) {
+    uint64_t nc = v->cap ? v->cap * 2 : 1024;
+    uint32_t *p = (uint32_t *)realloc(v->a, nc * sizeof(uint32_t));
+    if (!p) { v->oom = 1; return; }
+    v->a = p; v->cap = nc;
+  }
+  v->a[v->n++] = x;
+}
+
+static void v64_push(vec64 *v, uint64_t x) {
+  if (v->oom) return;
+  if (v->n == v->cap) {
+    uint64_t nc = v->cap ? v->cap * 2 : 1024;
+    uint64_t *p = (uint64_t *)realloc(v->a, nc * sizeof(uint64_t));
+    if (!p) { v->oom = 1; return; }
+    v->a = p; v->cap = nc;
+  }
+  v->a[v->n++] = x;
+}
+
+/* ---- graph helpers ------------------------------------------------------ */
+
+static int adjacent(const graph *g, uint32_t u, uint32_t v) {
+  uint64_t lo = g->rp[u], hi = g->rp[u + 1];
+  while (lo < hi) {
+    uint64_t mid = lo + (hi - lo) / 2;
+    uint32_t x = g->col[mid];
+    if (x == v) return 1;
+    if (x < v) lo = mid + 1; else hi = mid;
+  }
+  return 0;
+}
+
+int ndo_validate_csr(uint32_t n, const uint64_t *row_ptr, const uint32_t *col) {
+  if (!row_ptr) return NDO_E_INVALID_ARG;
+  if (row_ptr[0] != 0) return NDO_E_BAD_GRAPH;
+  for (uint32_t u = 0; u < n; u++)
+    if (row_ptr[u + 1] < row_ptr[u]) return NDO_E_BAD_GRAPH;
+  if (row_ptr[n] && !col) return NDO_E_INVALID_ARG;
+  graph g = {n, row_ptr, col, 0};
+  for (uint32_t u = 0; u < n; u++) {
+    for (uint64_t j = row_ptr[u]; j < row_ptr[u + 1]; j++) {
+      uint32_t v = col[j];
+      if (v >= n || v == u) return NDO_E_BAD_GRAPH;
+      if (j > row_ptr[u] && col[j - 1] >= v) return NDO_E_BAD_GRAPH;
+      if (!adjacent(&g, v, u)) return NDO_E_BAD_GRAPH;
+    }
+  }
+  return NDO_OK;
+}
+
+/* ---- clique listing by depth-first search over forward neighbours ------- */
+
+/* Lists every q-clique once as an ascending tuple, in lexicographic order:
+ * tuple[0] runs over all vertices; tuple[d+1] runs over the common
+ * neighbours of tuple[0..d] that are larger than tuple[d]. */
+typedef void (*emit_fn)(const uint32_t *tuple, void *ctx);
+
+typedef struct {
+  const graph *g;
+  uint32_t q;
+  uint32_t tuple[MAXS];
+  uint32_t *cand[MAXS];
+  uint64_t ncand[MAXS];
+  emit_fn emit;
+  void *ctx;
+} lister;
+
+static void lister_rec(lister *L, uint32_t d) {
+  if (d == L->q) { L->emit(L->tuple, L->ctx); return; }
+  const graph *g = L->g;
+  for (uint64_t i = 0; i < L->ncand[d]; i++) {
+    uint32_t v = L->cand[d][i];
+    L->tuple[d] = v;
+    if (d + 1 < L->q) {
+      /* cand[d+1] = cand[d][i+1..] intersected with N(v) (both sorted) */
+      uint64_t a = i + 1, b = g->rp[v], be = g->rp[v + 1], k = 0;
+      while (a < L->ncand[d] && b < be) {
+        uint32_t x = L->cand[d][a], y = g->col[b];
+        if (x == y) { L->cand[d + 1][k++] = x; a++; b++; }
+        else if (x < y) a++;
+        else b++;
+      }
+      L->ncand[d + 1] = k;
+    }
+    lister_rec(L, d + 1);
+  }
+}
+
+static int list_cliques(const graph *g, uint32_t q, emit_fn emit, void *ctx) {
+  lister L;
+  memset(&L, 0, sizeof(L));
+  L.g = g; L.q = q; L.emit = emit; L.ctx = ctx;
+  uint64_t cap = g->maxdeg ? g->maxdeg : 1;
+  for (uint32_t d = 0; d < q; d++) {
+    L.cand[d] = (uint32_t *)malloc(cap * sizeof(uint32_t));
+    if (!L.cand[d]) { for (uint32_t e = 0; e < d; e++) free(L.cand[e]); return NDO_E_OOM; }
+  }
+  for (uint32_t v0 = 0; v0 < g->n; v0++) {
+    L.tuple[0] = v0;
+    if (q == 1) { emit(L.tuple, ctx); continue; }
+    uint64_t k = 0;
+    for (uint64_t j = g->rp[v0]; j < g->rp[v0 + 1]; j++)
+      if (g->col[j] > v0) L.cand[1][k++] = g->col[j];
+    L.ncand[1] = k;
+    lister_rec(&L, 1);
+  }
+  for (uint32_t d = 0; d < q; d++) free(L.cand[d]);
+  return NDO_OK;
+}
+
+/* ---- r-clique table (O1) and lookup ------------------------------------ */
+
+typedef struct {
+  uint32_t r;
+  uint64_t n_r;
+  uint32_t *t;   /* n_r * r, lexicographic */
+} rtable;
+
+typedef struct { vec32 v; uint32_t r; } rcollect;
+
+static void emit_rcollect(const uint32_t *tuple, void *ctx) {
+  rcollect *c = (rcollect *)ctx;
+  for (uint32_t i = 0; i < c->r; i++) v32_push(&c->v, tuple[i]);
+}
+
+static int tuple_cmp(const uint32_t *a, const uint32_t *b, uint32_t r) {
+  for (uint32_t i = 0; i < r; i++) {
+    if (a[i] < b[i]) return -1;
+    if (a[i] > b[i]) return 1;
+  }
+  return 0;
+}
+
+/* id of an ascending r-tuple, or NONE if it is not an r-clique */
+static uint64_t rlookup(const rtable *T, const uint32_t *tuple) {
+  if (T->r == 1) return tuple[0];
+  uint64_t lo = 0, hi = T->n_r;
+  while (lo < hi) {
+    uint64_t mid = lo + (hi - lo) / 2;
+    int c = tuple_cmp(T->t + mid * T->r, tuple, T->r);
+    if (c == 0) return mid;
+    if (c < 0) lo = mid + 1; else hi = mid;
+  }
+  return NONE;
+}
+
+/* ---- s-cliques containing a given r-clique ------------------------------ */
+
+/* For r-clique R (ascending tuple), calls fn(S, ctx) for every s-clique S
+ * containing R, with S as an ascending s-tuple. C(R) is the set of vertices
+ * adjacent to every vertex of R; the s-cliques containing R are R plus an
+ * (s-r)-clique inside C(R). */
+typedef void (*sfn)(const uint32_t *S, void *ctx);
+
+typedef struct {
+  const graph *g;
+  uint32_t r, s;
+  uint32_t *cand[MAXS + 1];
+  uint64_t ncand[MAXS + 1];
+  uint32_t ext[MAXS];
+  const uint32_t *R;
+  sfn fn;
+  void *ctx;
+} sscan;
+
+static void sscan_emit(sscan *X) {
+  uint32_t S[MAXS];
+  uint32_t i = 0, j = 0, k = 0, q = X->s - X->r;
+  while (i < X->r || j < q) {
+    if (j >= q || (i < X->r && X->R[i] < X->ext[j])) S[k++] = X->R[i++];
+    else S[k++] = X->ext[j++];
+  }
+  X->fn(S, X->ctx);
+}
+
+static void sscan_rec(sscan *X, uint32_t d) {
+  uint32_t q = X->s - X->r;
+  if (d == q) { sscan_emit(X); return; }
+  const graph *g = X->g;
+  for (uint64_t i = 0; i < X->ncand[d]; i++) {
+    uint32_t v = X->cand[d][i];
+    X->ext[d] = v;
+    if (d + 1 < q) {
+      uint64_t a = i + 1, b = g->rp[v], be = g->rp[v + 1], k = 0;
+      while (a < X->ncand[d] && b < be) {
+        uint32_t x = X->cand[d][a], y = g->col[b];
+        if (x == y) { X->cand[d + 1][k++] = x; a++; b++; }
+        else if (x < y) a++;
+        else b++;
+      }
+      X->ncand[d + 1] = k;
+    }
+    sscan_rec(X, d + 1);
+  }
+}
+
+static void for_each_sclique(sscan *X, const uint32_t *R) {
+  const graph *g = X->g;
+  X->R = R;
+  /* C(R): scan the row of R[0], keep vertices adjacent to all of R[1..] */
+  uint64_t k = 0;
+  for (uint64_t j = g->rp[R[0]]; j < g->rp[R[0] + 1]; j++) {
+    uint32_t w = g->col[j];
+    int ok = 1;
+    for (uint32_t t = 1; t < X->r && ok; t++) ok = adjacent(g, R[t], w);
+    if (ok) X->cand[0][k++] = w;
+  }
+  X->ncand[0] = k;
+  sscan_rec(X, 0);
+}
+
+static int sscan_init(sscan *X, const graph *g, uint32_t r, uint32_t s, sfn fn, void *ctx) {
+  memset(X, 0, sizeof(*X));
+  X->g = g; X->r = r; X->s = s; X->fn = fn; X->ctx = ctx;
+  uint64_t cap = g->maxdeg ? g->maxdeg : 1;
+  for (uint32_t d = 0; d <= s - r; d++) {
+    X->cand[d] = (uint32_t *)malloc(cap * sizeof(uint32_t));
+    if (!X->cand[d]) return NDO_E_OOM;
+  }
+  return NDO_OK;
+}
+
+static void sscan_free(sscan *X) {
+  for (uint32_t d = 0; d <= MAXS; d++) free(X->cand[d]);
+}
+
+/* r-subsets of an s-set, as bit masks */
+typedef struct { uint32_t nm; uint32_t mask[128]; } subsets;
+
+static void make_subsets(subsets *sb, uint32_t r, uint32_t s) {
+  sb->nm = 0;
+  for (uint32_t m = 0; m < (1u << s); m++)
+    if ((uint32_t)__builtin_popcount(m) == r) sb->mask[sb->nm++] = m;
+}
+
+static void subset_tuple(const uint32_t *S, uint32_t s, uint32_t mask, uint32_t *out) {
+  uint32_t k = 0;
+  for (uint32_t i = 0; i < s; i++)
+    if (mask & (1u << i)) out[k++] = S[i];
+}
+
+/* ---- O2: counting -------------------------------------------------------- */
+
+typedef struct {
+  const rtable *T;
+  uint32_t s;
+  subsets sb;
+  uint64_t *count;
+  uint64_t n_s;
+} counter;
+
+static void emit_count(const uint32_t *S, void *ctx) {
+  counter *c = (counter *)ctx;
+  uint32_t sub[MAXS];
+  c->n_s++;
+  for (uint32_t i = 0; i < c->sb.nm; i++) {
+    subset_tuple(S, c->s, c->sb.mask[i], sub);
+    uint64_t id = rlookup(c->T, sub);
+    c->count[id]++;   /* every subset of a clique is a clique, so id != NONE */
+  }
+}
+
+/* ---- union-find (sequential) -------------------------------------------- */
+
+static uint64_t uf_find(uint64_t *p, uint64_t x) {
+  uint64_t root = x;
+  while (p[root] != root) root = p[root];
+  while (p[x] != root) { uint64_t nx = p[x]; p[x] = root; x = nx; }
+  return root;
+}
+
+static void uf_union(uint64_t *p, uint64_t a, uint64_t b) {
+  a = uf_find(p, a);
+  b = uf_find(p, b);
+  if (a == b) return;
+  if (a < b) p[b] = a; else p[a] = b;
+}
+
+/* ---- O3: sequential peel ------------------------------------------------- */
+
+typedef struct {
+  const rtable *T;
+  uint32_t s;
+  uint64_t self;
+  subsets sb;
+  uint64_t *deg;     /* current degree */
+  uint8_t *gone;     /* 1 once peeled */
+  uint64_t *vert, *pos, *bin;
+  uint64_t nbin;
+  uint64_t floor_deg;  /* degree of the r-clique being peeled */
+  /* scratch for the current s-clique */
+  uint64_t others[128];
+} peeler;
+
+/* Batagelj-Zaversnik bucket move of x from bin d to bin d-1. Degrees are
+ * never lowered below the degree of the r-clique being peeled, which leaves
+ * every core number unchanged: a core number is the running maximum of the
+ * minimum degree, and that maximum is already at least the current one. */
+static void bz_decrement(peeler *P, uint64_t x, uint64_t floor_deg) {
+  uint64_t dx = P->deg[x];
+  if (dx <= floor_deg) return;
+  uint64_t px = P->pos[x];
+  uint64_t pw = P->bin[dx];
+  uint64_t w = P->vert[pw];
+  if (w != x) {
+    P->pos[x] = pw; P->vert[pw] = x;
+    P->pos[w] = px; P->vert[px] = w;
+  }
+  P->bin[dx]++;
+  P->deg[x] = dx - 1;
+}
+
+static void emit_peel(const uint32_t *S, void *ctx) {
+  peeler *P = (peeler *)ctx;
+  uint32_t sub[MAXS];
+  uint32_t no = 0;
+  for (uint32_t i = 0; i < P->sb.nm; i++) {
+    subset_tuple(S, P->s, P->sb.mask[i], sub);
+    uint64_t id = rlookup(P->T, sub);
+    if (id == P->self) continue;
+    if (P->gone[id]) return;           /* S was destroyed earlier */
+    P->others[no++] = id;
+  }
+  for (uint32_t i = 0; i < no; i++) bz_decrement(P, P->others[i], P->floor_deg);
+}
+
+/* ---- O4: hierarchy --------------------------------------------------------- */
+
+typedef struct {
+  const rtable *T;
+  uint32_t s;
+  uint64_t self;
+  subsets sb;
+  const uint8_t *active;
+  uint64_t *uf;
+  uint64_t *stamp;
+  uint64_t level;
+  vec64 *pieces;
+  int do_union;
+} linker;
+
+static void emit_link(const uint32_t *S, void *ctx) {
+  linker *K = (linker *)ctx;
+  uint32_t sub[MAXS];
+  for (uint32_t i = 0; i < K->sb.nm; i++) {
+    subset_tuple(S, K->s, K->sb.mask[i], sub);
+    uint64_t id = rlookup(K->T, sub);
+    if (id == K->self || !K->active[id]) continue;
+    if (K->do_union) {
+      uf_union(K->uf, K->self, id);
+    } else {
+      uint64_t p = uf_find(K->uf, id);
+      if (K->stamp[p] != K->level) { K->stamp[p] = K->level; v64_push(K->pieces, p); }
+    }
+  }
+}
+
+typedef struct { uint64_t key; uint64_t val; } kv;
+
+static int kv_cmp(const void *a, const void *b) {
+  const kv *x = (const kv *)a, *y = (const kv *)b;
+  if (x->key != y->key) return x->key < y->key ? -1 : 1;
+  if (x->val != y->val) return x->val < y->val ? -1 : 1;
+  return 0;
+}
+
+typedef struct { uint64_t level, minleaf, node; } nodekey;
+
+static int nodekey_cmp(const void *a, const void *b) {
+  const nodekey *x = (const nodekey *)a, *y = (const nodekey *)b;
+  if (x->level != y->level) return x->level < y->level ? -1 : 1;
+  if (x->minleaf != y->minleaf) return x->minleaf < y->minleaf ? -1 : 1;
+  return 0;
+}
+
+/* ---- driver ---------------------------------------------------------------- */
+
+void ndo_free(ndo_result *res) {
+  if (!res) return;
+  free(res->rcliques);
+  free(res->count);
+  free(res->coreness);
+  free(res->peel_order);
+  free(res->parent);
+  free(res->level);
+  memset(res, 0, sizeof(*res));
+}
+
+static int build_graph(graph *g, uint32_t n, const uint64_t *row_ptr, const uint32_t *col) {
+  int st = ndo_validate_csr(n, row_ptr, col);
+  if (st != NDO_OK) return st;
+  g->n = n; g->rp = row_ptr; g->col = col; g->maxdeg = 0;
+  for (uint32_t u = 0; u < n; u++) {
+    uint64_t d = row_ptr[u + 1] - row_ptr[u];
+    if (d > g->maxdeg) g->maxdeg = d;
+  }
+  return NDO_OK;
+}
+
+static int do_count(const graph *g, uint32_t r, uint32_t s, ndo_result *out, rtable *T) {
+  rcollect rc;
+  memset(&rc, 0, sizeof(rc));
+  rc.r = r;
+  int st = list_cliques(g, r, emit_rcollect, &rc);
+  if (st != NDO_OK || rc.v.oom) { free(rc.v.a); return NDO_E_OOM; }
+  T->r = r;
+  T->n_r = rc.v.n / r;
+  T->t = rc.v.a;
+  out->n_r = T->n_r;
+  out->rcliques = T->t;
+  if (!out->rcliques) out->rcliques = (uint32_t *)malloc(sizeof(uint32_t));
+  T->t = out->rcliques;
+  out->count = (uint64_t *)calloc(T->n_r ? T->n_r : 1, sizeof(uint64_t));
+  if (!out->count) return NDO_E_OOM;
+  counter c;
+  memset(&c, 0, sizeof(c));
+  c.T = T; c.s = s; c.count = out->count;
+  make_subsets(&c.sb, r, s);
+  st = list_cliques(g, s, emit_count, &c);
+  if (st != NDO_OK) return st;
+  out->n_s = c.n_s;
+  return NDO_OK;
+}
+
+int ndo_count(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
+              uint32_t r, uint32_t s, ndo_result *out) {
+  if (!out) return NDO_E_INVALID_ARG;
+  memset(out, 0, sizeof(*out));
+  if (r < 1 || s <= r || s > MAXS) return NDO_E_INVALID_ARG;
+  graph g;
+  int st = build_graph(&g, n, row_ptr, col);
+  if (st != NDO_OK) return st;
+  out->n = n; out->r = r; out->s = s;
+  rtable T;
+  st = do_count(&g, r, s, out, &T);
+  if (st != NDO_OK) ndo_free(out);
+  return st;
+}
+
+int ndo_decompose(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
+                  uint32_t r, uint32_t s, ndo_result *out) {
+  if (!out) return NDO_E_INVALID_ARG;
+  memset(out, 0, sizeof(*out));
+  if (r < 1 || s <= r || s > MAXS) return NDO_E_INVALID_ARG;
+  graph g;
+  int st = build_graph(&g, n, row_ptr, col);
+  if (st != NDO_OK) return st;
+  out->n = n; out->r = r; out->s = s;
+
+  /* O1 + O2 */
+  double t0 = now_s();
+  rtable T;
+  st = do_count(&g, r, s, out, &T);
+  if (st != NDO_OK) { ndo_free(out); return st; }
+  const uint64_t nr = T.n_r;
+  const uint64_t nr1 = nr ? nr : 1;
+  double t1 = now_s();
+  out->t_count = t1 - t0;
+
+  /* O3: sequential peel with Batagelj-Zaversnik bins */
+  out->coreness = (uint64_t *)calloc(nr1, sizeof(uint64_t));
+  out->peel_order = (uint64_t *)calloc(nr1, sizeof(uint64_t));
+  peeler P;
+  memset(&P, 0, sizeof(P));
+  P.T = &T; P.s = s;
+  make_subsets(&P.sb, r, s);
+  P.deg = (uint64_t *)malloc(nr1 * sizeof(uint64_t));
+  P.gone = (uint8_t *)calloc(nr1, 1);
+  P.vert = (uint64_t *)malloc(nr1 * sizeof(uint64_t));
+  P.pos = (uint64_t *)malloc(nr1 * sizeof(uint64_t));
+  uint64_t maxd = 0;
+  for (uint64_t i = 0; i < nr; i++) if (out->count[i] > maxd) maxd = out->count[i];
+  P.nbin = maxd + 2;
+  P.bin = (uint64_t *)calloc(P.nbin, sizeof(uint64_t));
+  sscan X;
+  int sst = sscan_init(&X, &g, r, s, emit_peel, &P);
+  if (!out->coreness || !out->peel_order || !P.deg || !P.gone || !P.vert || !P.pos ||
+      !P.bin || sst != NDO_OK) {
+    free(P.deg); free(P.gone); free(P.vert); free(P.pos); free(P.bin); sscan_free(&X);
+    ndo_free(out);
+    return NDO_E_OOM;
+  }
+  for (uint64_t i = 0; i < nr; i++) { P.deg[i] = out->count[i]; P.bin[P.deg[i]]++; }
+  {
+    uint64_t start = 0;
+    for (uint64_t d = 0; d < P.nbin; d++) { uint64_t c = P.bin[d]; P.bin[d] = start; start += c; }
+    for (uint64_t i = 0; i < nr; i++) { P.pos[i] = P.bin[P.deg[i]]++; P.vert[P.pos[i]] = i; }
+    for (uint64_t d = P.nbin - 1; d > 0; d--) P.bin[d] = P.bin[d - 1];
+    P.bin[0] = 0;
+  }
+  uint64_t k = 0;
+  uint32_t tup[MAXS];
+  for (uint64_t i = 0; i < nr; i++) {
+    uint64_t R = P.vert[i];
+    uint64_t d = P.deg[R];
+    if (d > k) k = d;
+    out->coreness[R] = k;
+    out->peel_order[i] = R;
+    P.gone[R] = 1;
+    P.self = R;
+    P.floor_deg = d;
+    memcpy(tup, T.t + R * r, r * sizeof(uint32_t));
+    for_each_sclique(&X, tup);
+  }
+  out->k = k;
+  free(P.deg); free(P.vert); free(P.pos); free(P.bin);
+  double t2 = now_s();
+  out->t_peel = t2 - t1;
+
+  /* O4: hierarchy, levels from k down to 1 (reverse peel order is sorted by
+   * non-increasing core number). */
+  uint64_t *uf = (uint64_t *)malloc(nr1 * sizeof(uint64_t));
+  uint64_t *stamp = (uint64_t *)malloc(nr1 * sizeof(uint64_t));
+  uint64_t *top = (uint64_t *)malloc(nr1 * sizeof(uint64_t));
+  uint64_t *par = (uint64_t *)malloc(2 * nr1 * sizeof(uint64_t));
+  uint64_t *minleaf = (uint64_t *)malloc(2 * nr1 * sizeof(uint64_t));
+  uint64_t *nlevel = (uint64_t *)malloc(nr1 * sizeof(uint64_t));
+  uint8_t *active = P.gone;   /* reuse: cleared below */
+  vec64 pieces;
+  memset(&pieces, 0, sizeof(pieces));
+  if (!uf || !stamp || !top || !par || !minleaf || !nlevel) {
+    free(uf); free(stamp); free(top); free(par); free(minleaf); free(nlevel); free(active);
+    sscan_free(&X); ndo_free(out);
+    return NDO_E_OOM;
+  }
+  memset(active, 0, nr1);
+  for (uint64_t i = 0; i < nr; i++) { uf[i] = i; stamp[i] = NONE; top[i] = i; }
+  for (uint64_t i = 0; i < 2 * nr1; i++) { par[i] = NONE; minleaf[i] = i; }
+  uint64_t nint = 0;
+  linker K;
+  memset(&K, 0, sizeof(K));
+  K.T = &T; K.s = s; K.active = active; K.uf = uf; K.stamp = stamp; K.pieces = &pieces;
+  make_subsets(&K.sb, r, s);
+  X.fn = emit_link;
+  X.ctx = &K;
+  uint64_t hi = nr;   /* process peel_order[lo..hi) in reverse */
+  int oom = 0;
+  while (hi > 0) {
+    uint64_t c = out->coreness[out->peel_order[hi - 1]];
+    uint64_t lo = hi;
+    while (lo > 0 && out->coreness[out->peel_order[lo - 1]] == c) lo--;
+    if (c == 0) break;   /* core-0 r-cliques lie in no s-clique: root leaves */
+    for (uint64_t i = lo; i < hi; i++) active[out->peel_order[i]] = 1;
+    /* pieces: the level-c r-cliques themselves and the current components
+     * (of levels > c) they touch */
+    pieces.n = 0;
+    K.level = c;
+    K.do_union = 0;
+    for (uint64_t i = lo; i < hi; i++) {
+      uint64_t R = out->peel_order[i];
+      if (stamp[R] != c) { stamp[R] = c; v64_push(&pieces, R); }
+      K.self = R;
+      memcpy(tup, T.t + R * r, r * sizeof(uint32_t));
+      for_each_sclique(&X, tup);
+    }
+    K.do_union = 1;
+    for (uint64_t i = lo; i < hi; i++) {
+      uint64_t R = out->peel_order[i];
+      K.self = R;
+      memcpy(tup, T.t + R * r, r * sizeof(uint32_t));
+      for_each_sclique(&X, tup);
+    }
+    if (pieces.oom) { oom = 1; break; }
+    /* group the pieces by their new root; groups of >= 2 pieces are the new
+     * components of size >= 2, i.e. the level-c tree nodes */
+    kv *grp = (kv *)malloc((pieces.n ? pieces.n : 1) * sizeof(kv));
+    if (!grp) { oom = 1; break; }
+    for (uint64_t i = 0; i < pieces.n; i++) {
+      grp[i].key = uf_find(uf, pieces.a[i]);
+      grp[i].val = pieces.a[i];
+    }
+    qsort(grp, pieces.n, sizeof(kv), kv_cmp);
+    for (uint64_t i = 0; i < pieces.n;) {
+      uint64_t j = i;
+      while (j < pieces.n && grp[j].key == grp[i].key) j++;
+      if (j - i >= 2) {
+        uint64_t node = nr + nint;
+        nlevel[nint] = c;
+        nint++;
+        uint64_t ml = NONE;
+        for (uint64_t t = i; t < j; t++) {
+          uint64_t child = top[grp[t].val];
+          par[child] = node;
+          if (minleaf[child] < ml) ml = minleaf[child];
+        }
+        minleaf[node] = ml;
+        top[grp[i].key] = node;
+      }
+      i = j;
+    }
+    free(grp);
+    hi = lo;
+  }
+  sscan_free(&X);
+  free(pieces.a); free(uf); free(stamp); free(top); free(active);
+  if (oom) { free(par); free(minleaf); free(nlevel); ndo_free(out); return NDO_E_OOM; }
+
+  /* O5: canonical numbering by (level, min leaf) */
+  nodekey *keys = (nodekey *)malloc((nint ? nint : 1) * sizeof(nodekey));
+  uint64_t *canon = (uint64_t *)malloc((nint ? nint : 1) * sizeof(uint64_t));
+  out->parent = (uint64_t *)malloc((nr + nint ? nr + nint : 1) * sizeof(uint64_t));
+  out->level = (uint64_t *)malloc((nint ? nint : 1) * sizeof(uint64_t));
+  if (!keys || !canon || !out->parent || !out->level) {
+    free(keys); free(canon); free(par); free(minleaf); free(nlevel); ndo_free(out);
+    return NDO_E_OOM;
+  }
+  for (uint64_t i = 0; i < nint; i++) {
+    keys[i].level = nlevel[i];
+    keys[i].minleaf = minleaf[nr + i];
+    keys[i].node = i;
+  }
+  qsort(keys, nint, sizeof(nodekey), nodekey_cmp);
+  for (uint64_t i = 0; i < nint; i++) canon[keys[i].node] = nr + i;
+  for (uint64_t x = 0; x < nr; x++)
+    out->parent[x] = par[x] == NONE ? NONE : canon[par[x] - nr];
+  for (uint64_t i = 0; i < nint; i++) {
+    uint64_t p = par[nr + i];
+    out->parent[canon[i]] = p == NONE ? NONE : canon[p - nr];
+    out->level[canon[i] - nr] = nlevel[i];
+  }
+  out->n_int = nint;
+  free(keys); free(canon); free(par); free(minleaf); free(nlevel);
+  out->t_tree = now_s() - t2;
+  return NDO_OK;
+}

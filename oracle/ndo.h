@@ -1,0 +1,89 @@
+/*
+ * ndo.h -- plain sequential CPU oracle for exact (r,s) nucleus decomposition
+ * and its hierarchy.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product library may include,
+ * link or call this code; only the tests, the smoke check and the CPU
+ * baseline of the benchmark use it. It shares no source with the GPU path.
+ *
+ * What it computes (Shi, Dhulipala, Shun, "Parallel Algorithms for
+ * Hierarchical Nucleus Decomposition", arXiv 2306.08623):
+ *
+ *  - r-cliques in lexicographic order of their ascending vertex tuples; the
+ *    position in that order is the canonical r-clique id.
+ *  - the s-clique degree of every r-clique (Section 3, the number of
+ *    s-cliques containing it) and the number of s-cliques n_s.
+ *  - the (r,s)-clique core number of every r-clique (Section 3 definition),
+ *    computed by the sequential minimum-degree peeling that Section 6 (proof
+ *    of Lemma 1) describes: repeatedly remove an unpeeled r-clique of minimum
+ *    current s-clique degree; its core number is the largest minimum seen so
+ *    far; removing it destroys every s-clique it belongs to, which lowers the
+ *    degree of the other still-present r-cliques of those s-cliques.
+ *  - the nucleus hierarchy (Section 5, Algorithm 1 semantics; Section 7.4
+ *    practical form): for c = k down to 1, union-find over r-cliques with
+ *    core number >= c, joining two r-cliques when one s-clique contains both
+ *    (s-clique-adjacent, Section 3); every component of that graph that
+ *    contains a core-c r-clique and has at least two r-cliques is a tree node
+ *    of level c. Parents with a single child are not created (Section 7.3,
+ *    the remark on unary parents).
+ *  - the canonical tree: leaves 0..n_r-1 are the canonical r-clique ids;
+ *    internal nodes are numbered n_r + rank of (level, smallest leaf id in
+ *    the node) ascending; parent = UINT64_MAX for roots.
+ *
+ * Everything is integer arithmetic; counts and core numbers are uint64.
+ * Supported: 1 <= r < s <= 7.
+ */
+#ifndef NDO_H
+#define NDO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  NDO_OK = 0,
+  NDO_E_INVALID_ARG = 1,
+  NDO_E_BAD_GRAPH = 2,
+  NDO_E_OOM = 3,
+};
+
+typedef struct ndo_result {
+  uint32_t n, r, s;
+  uint64_t n_r;          /* number of r-cliques */
+  uint64_t n_s;          /* number of s-cliques */
+  uint32_t *rcliques;    /* n_r * r vertex ids, tuples ascending, lexicographic */
+  uint64_t *count;       /* n_r: s-clique degree before any peeling */
+  uint64_t *coreness;    /* n_r: (r,s)-clique core number */
+  uint64_t *peel_order;  /* n_r: r-clique ids in the order the peel removed them */
+  uint64_t k;            /* max core number (0 if n_r == 0) */
+  uint64_t n_int;        /* internal nodes of the canonical tree */
+  uint64_t *parent;      /* n_r + n_int: parent node, UINT64_MAX for roots */
+  uint64_t *level;       /* n_int: level of internal node n_r + i */
+  double t_count;        /* seconds: r-clique listing + s-clique counting */
+  double t_peel;         /* seconds: sequential peel */
+  double t_tree;         /* seconds: hierarchy + canonical numbering */
+} ndo_result;
+
+/* Returns NDO_OK if (row_ptr, col) is a symmetric CSR over 0..n-1 with each
+ * row strictly increasing (so no duplicates) and no self-loops. */
+int ndo_validate_csr(uint32_t n, const uint64_t *row_ptr, const uint32_t *col);
+
+/* Full decomposition. On success *out owns heap arrays; release with
+ * ndo_free. On error *out is zeroed. */
+int ndo_decompose(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
+                  uint32_t r, uint32_t s, ndo_result *out);
+
+/* Only the r-clique listing and the s-clique counts (rcliques, count, n_r,
+ * n_s); coreness / tree fields stay NULL. */
+int ndo_count(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
+              uint32_t r, uint32_t s, ndo_result *out);
+
+void ndo_free(ndo_result *res);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NDO_H */

@@ -1,0 +1,284 @@
+"""Pins for the CPU oracle: brute force on tiny graphs, closed forms, library
+routines (networkx) and invariants from the paper. None of these share code
+with the oracle (``oracle/ndo.c``)."""
+from __future__ import annotations
+
+import itertools
+from math import comb
+
+import networkx as nx
+import numpy as np
+import pytest
+
+import brute
+import oracle
+from paper_2306_08623_amd import inputs as I
+
+NONE = 0xFFFFFFFFFFFFFFFF
+RS_SMALL = [(1, 2), (1, 3), (2, 3), (1, 4), (2, 4), (3, 4), (2, 5), (3, 5)]
+
+
+def _graph_from_mask(n, mask):
+    pairs = list(itertools.combinations(range(n), 2))
+    e = [pairs[i] for i in range(len(pairs)) if mask >> i & 1]
+    return I.from_edges(n, e)
+
+
+def _check_against_brute(g, r, s):
+    d = oracle.decompose(g, r, s)
+    b = brute.brute_all(g, r, s)
+    assert [tuple(t) for t in d.rcliques.tolist()] == b["rcliques"]
+    assert d.n_s == b["n_s"]
+    assert d.count.tolist() == b["count"]
+    assert d.coreness.tolist() == b["coreness"]
+    assert d.parent.tolist() == b["parent"], (g.edges().tolist(), r, s)
+    assert d.level.tolist() == b["level"]
+
+
+def test_all_graphs_on_five_vertices():
+    """Exhaustive: all 1,024 labelled graphs on 5 vertices, every (r,s) with
+    r < s <= 5."""
+    for mask in range(1 << 10):
+        g = _graph_from_mask(5, mask)
+        for r, s in [(1, 2), (1, 3), (2, 3), (1, 4), (2, 4), (3, 4), (2, 5), (3, 5), (4, 5)]:
+            _check_against_brute(g, r, s)
+
+
+def test_random_graphs_on_six_vertices():
+    rng = np.random.default_rng(11)
+    for mask in rng.choice(1 << 15, size=250, replace=False):
+        g = _graph_from_mask(6, int(mask))
+        for r, s in RS_SMALL:
+            _check_against_brute(g, r, s)
+
+
+@pytest.mark.parametrize("n,p,seed", [(8, 0.5, 1), (9, 0.6, 2), (10, 0.45, 3), (11, 0.5, 4),
+                                      (12, 0.4, 5), (12, 0.7, 6), (13, 0.55, 7)])
+def test_random_gnp_small(n, p, seed):
+    g = I.gnp(n, p, seed)
+    for r, s in RS_SMALL:
+        _check_against_brute(g, r, s)
+
+
+def test_planted_small():
+    """A graph with overlapping planted cliques: deep, non-trivial trees."""
+    g = I.er_planted(14, 0.15, 3, 4, 7, seed=9)
+    for r, s in [(1, 2), (2, 3), (3, 4), (2, 4), (1, 3)]:
+        _check_against_brute(g, r, s)
+
+
+# ---------------------------------------------------------------------------
+# closed forms
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", range(1, 9))
+@pytest.mark.parametrize("r,s", [(1, 2), (1, 3), (2, 3), (1, 4), (2, 4), (3, 4), (2, 5), (3, 6)])
+def test_complete_graph(n, r, s):
+    """K_n: n_r = C(n,r), n_s = C(n,s); every r-clique lies in C(n-r, s-r)
+    s-cliques and has that core number; one node holds every r-clique."""
+    d = oracle.decompose(I.complete(n), r, s)
+    assert d.n_r == comb(n, r)
+    assert d.n_s == comb(n, s)
+    want = comb(n - r, s - r) if n >= s else 0
+    assert set(d.count.tolist()) <= {want}
+    assert set(d.coreness.tolist()) <= {want}
+    if n >= s and d.n_r >= 2:
+        assert d.n_int == 1
+        assert d.level.tolist() == [want]
+        assert d.parent[: d.n_r].tolist() == [d.n_r] * d.n_r
+        assert d.parent[d.n_r] == NONE
+    else:
+        assert d.n_int == 0
+        assert all(p == NONE for p in d.parent.tolist())
+
+
+def test_disjoint_cliques_two_roots():
+    g = I.disjoint_union(I.complete(5), I.complete(7))
+    for r, s in [(1, 2), (2, 3), (3, 4), (2, 4)]:
+        d = oracle.decompose(g, r, s)
+        a, b = comb(5, r), comb(7, r)
+        assert d.n_r == a + b
+        assert d.n_int == 2
+        assert sorted(d.level.tolist()) == sorted([comb(5 - r, s - r), comb(7 - r, s - r)])
+        assert d.parent[d.n_r] == NONE and d.parent[d.n_r + 1] == NONE
+        # leaves of the first clique share one parent, the second another
+        assert len(set(d.parent[:a].tolist())) == 1
+        assert len(set(d.parent[a:a + b].tolist())) == 1
+        assert d.parent[0] != d.parent[a]
+
+
+def test_edgeless_and_empty():
+    for n in (0, 1, 5):
+        g = I.empty(n)
+        d = oracle.decompose(g, 1, 2)
+        assert d.n_r == n and d.n_s == 0 and d.n_int == 0
+        assert d.coreness.tolist() == [0] * n
+        d = oracle.decompose(g, 2, 3)
+        assert d.n_r == 0 and d.n_int == 0
+
+
+def test_star_and_cycle():
+    d = oracle.decompose(I.star(7), 1, 2)
+    assert d.coreness.tolist() == [1] * 7
+    assert d.n_int == 1 and d.level.tolist() == [1]
+    d = oracle.decompose(I.cycle(9), 1, 2)
+    assert d.coreness.tolist() == [2] * 9
+    assert d.n_int == 1 and d.level.tolist() == [2]
+    d = oracle.decompose(I.cycle(9), 2, 3)
+    assert d.coreness.tolist() == [0] * 9 and d.n_int == 0
+    d = oracle.decompose(I.cycle(3), 2, 3)
+    assert d.coreness.tolist() == [1] * 3 and d.n_int == 1
+
+
+def test_two_k5_bridge_pairwise_reading():
+    """Two K5 sharing vertex 0 plus edge (1,5). The 20 K5 edges have core 3
+    and (1,5) has core 1. s-clique adjacency is pairwise (Section 3): the K5
+    edges (0,1) and (0,5) share triangle {0,1,5}, so all 20 K5 edges form one
+    level-3 node, under a level-1 node that adds (1,5)."""
+    d = oracle.decompose(I.two_k5_bridge(), 2, 3)
+    tup = [tuple(t) for t in d.rcliques.tolist()]
+    bridge = tup.index((1, 5))
+    core = d.coreness.tolist()
+    assert core[bridge] == 1
+    assert all(c == 3 for i, c in enumerate(core) if i != bridge)
+    assert d.n_int == 2
+    assert d.level.tolist() == [1, 3]
+    n_r = d.n_r
+    lvl1, lvl3 = n_r, n_r + 1
+    assert d.parent[bridge] == lvl1
+    assert all(d.parent[i] == lvl3 for i in range(n_r) if i != bridge)
+    assert d.parent[lvl3] == lvl1 and d.parent[lvl1] == NONE
+
+
+# ---------------------------------------------------------------------------
+# library routines
+# ---------------------------------------------------------------------------
+
+def _nx(g):
+    G = nx.Graph()
+    G.add_nodes_from(range(g.n))
+    G.add_edges_from(g.edges().tolist())
+    return G
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_kcore_equals_networkx(seed):
+    """(1,2) nucleus decomposition is the k-core decomposition (Section 3)."""
+    g = I.er_planted(300, 0.03, 5, 5, 12, seed)
+    d = oracle.decompose(g, 1, 2)
+    cn = nx.core_number(_nx(g))
+    assert d.coreness.tolist() == [cn[v] for v in range(g.n)]
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_ktruss_equals_networkx(seed):
+    """(2,3) nucleus decomposition is the k-truss decomposition (Section 3).
+    The paper's k counts triangles; networkx's k-truss counts k-2 triangles
+    per edge, so an edge is in networkx's k-truss iff its core number is at
+    least k-2."""
+    g = I.er_planted(120, 0.06, 4, 5, 10, seed)
+    d = oracle.decompose(g, 2, 3)
+    G = _nx(g)
+    tup = {tuple(t): i for i, t in enumerate(d.rcliques.tolist())}
+    for k in range(3, int(d.k) + 4):
+        T = nx.k_truss(G, k)
+        in_truss = {tuple(sorted(e)) for e in T.edges()}
+        want = {t for t, i in tup.items() if d.coreness[i] >= k - 2}
+        assert in_truss == want, k
+
+
+def test_triangle_counts_equal_networkx():
+    """(1,3) s-clique degree of a vertex is its triangle count."""
+    g = I.er_planted(200, 0.05, 4, 5, 10, 5)
+    d = oracle.count(g, 1, 3)
+    tri = nx.triangles(_nx(g))
+    assert d.count.tolist() == [tri[v] for v in range(g.n)]
+    assert d.n_s == sum(tri.values()) // 3
+
+
+def test_four_clique_count_equals_networkx():
+    g = I.er_planted(60, 0.15, 3, 5, 9, 6)
+    d = oracle.count(g, 1, 4)
+    n4 = sum(1 for c in nx.enumerate_all_cliques(_nx(g)) if len(c) == 4)
+    assert d.n_s == n4
+
+
+# ---------------------------------------------------------------------------
+# invariants (Sections 5 and 6)
+# ---------------------------------------------------------------------------
+
+def _components_exact(n_r, members, nd, leaves, level):
+    """True iff ``leaves`` is exactly one connected component of the graph of
+    r-cliques with core >= level under s-clique adjacency."""
+    nbrs = [set() for _ in range(n_r)]
+    for ids in members:
+        for a, b in itertools.combinations(ids, 2):
+            nbrs[a].add(b)
+            nbrs[b].add(a)
+    start = next(iter(leaves))
+    seen = {start}
+    stack = [start]
+    while stack:
+        x = stack.pop()
+        for y in nbrs[x]:
+            if nd[y] >= level and y not in seen:
+                seen.add(y)
+                stack.append(y)
+    return seen == set(leaves)
+
+
+@pytest.mark.parametrize("r,s", [(1, 2), (2, 3), (3, 4), (2, 4), (1, 3)])
+def test_invariants_medium(r, s):
+    g = I.er_planted(90, 0.08, 4, 5, 11, 21)
+    d = oracle.decompose(g, r, s)
+    cnt = d.count.astype(np.int64)
+    nd = d.coreness.astype(np.int64)
+    assert int(cnt.sum()) == comb(s, r) * d.n_s            # each S has C(s,r) r-cliques
+    assert np.all(nd <= cnt)
+    assert int(nd.sum()) <= comb(s, r) * d.n_s             # Section 5 work bound
+    seq = nd[d.peel_order.astype(np.int64)]
+    assert np.all(np.diff(seq) >= 0)                       # monotone along the peel
+    # tree: every node is exactly a component of its level's graph; children
+    # levels exceed the parent's; node level = min core of its leaves
+    adj = brute.adjacency_sets(g)
+    R, S, _, members = brute.s_clique_degrees(adj, r, s)
+    n_r = d.n_r
+    par = d.parent.astype(object)
+    kids = {}
+    for x, p in enumerate(d.parent.tolist()):
+        if p != NONE:
+            kids.setdefault(p, []).append(x)
+
+    def leafset(x):
+        if x < n_r:
+            return {x}
+        out = set()
+        for c in kids.get(x, []):
+            out |= leafset(c)
+        return out
+
+    for i in range(d.n_int):
+        node = n_r + i
+        lv = int(d.level[i])
+        lf = leafset(node)
+        assert len(lf) >= 2 and len(kids[node]) >= 2
+        assert min(nd[list(lf)]) == lv
+        assert _components_exact(n_r, members, nd.tolist(), lf, lv)
+        for c in kids[node]:
+            if c >= n_r:
+                assert d.level[c - n_r] > lv
+        p = par[node]
+        if p != NONE:
+            assert d.level[p - n_r] < lv
+
+
+def test_rejects_bad_graphs():
+    rp = np.array([0, 1, 1], dtype=np.uint64)
+    col = np.array([1], dtype=np.uint32)     # asymmetric
+    from paper_2306_08623_amd.inputs import CSR
+    assert oracle.validate(CSR(2, rp, col)) == oracle.NDO_E_BAD_GRAPH
+    rp = np.array([0, 1, 2], dtype=np.uint64)
+    col = np.array([0, 0], dtype=np.uint32)  # self-loop
+    assert oracle.validate(CSR(2, rp, col)) == oracle.NDO_E_BAD_GRAPH
+    with pytest.raises(oracle.OracleError):
+        oracle.decompose(I.complete(4), 2, 2)
