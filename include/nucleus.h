@@ -1,0 +1,155 @@
+/*
+ * nucleus.h -- C ABI of the MI355X (gfx950) exact (r,s) nucleus decomposition
+ * library: coreness of every r-clique plus the nucleus hierarchy tree.
+ *
+ * Method: Shi, Dhulipala, Shun, "Parallel Algorithms for Hierarchical Nucleus
+ * Decomposition" (arXiv 2306.08623). The library runs the interleaved
+ * framework of Section 7.1 (Algorithm 3) with the efficient link and tree
+ * construction of Section 7.3 (Algorithm 5) on one GPU:
+ *   orient the graph (Section 3, low out-degree orientation), count the
+ *   s-cliques of every r-clique, peel r-cliques in rounds of minimum count
+ *   while linking s-clique-adjacent r-cliques into a union-find plus the
+ *   "nearest lower core" table L, then build the tree from uf and L.
+ *
+ * Definitions (Section 3):
+ *   - an r-clique's s-clique degree is the number of s-cliques containing it;
+ *   - its core number is the largest c such that it lies in a c-(r,s)
+ *     nucleus;
+ *   - two r-cliques are s-clique-adjacent when one s-clique contains both;
+ *   - the hierarchy nests, for every c, the connected components of the
+ *     graph on r-cliques of core >= c under s-clique adjacency.
+ *
+ * Output conventions (identical to the reference CPU oracle used by the
+ * tests):
+ *   - r-cliques are ascending vertex tuples; their canonical index is their
+ *     position in lexicographic order;
+ *   - the tree is canonical: leaves 0..n_r-1 are the r-cliques; internal
+ *     nodes n_r..n_r+n_int-1 are the components of size >= 2, each labelled
+ *     with its level (the smallest core number inside it), numbered by
+ *     ascending (level, smallest leaf index); a node's parent is the
+ *     smallest node strictly containing it; roots have parent UINT64_MAX.
+ *     Parents with a single child do not appear (Section 7.3 remark).
+ *
+ * Threading: one context per host thread; all device work of a context is
+ * ordered on the context's HIP stream. No exception crosses this ABI.
+ * Errors: every call returns an nd_status; after an error the context stays
+ * usable but the results of the failed decomposition are invalid.
+ */
+#ifndef NUCLEUS_H
+#define NUCLEUS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum nd_status {
+  ND_OK = 0,
+  ND_E_INVALID_ARG = 1,   /* NULL pointer, r/s out of range, bad sizes       */
+  ND_E_BAD_GRAPH = 2,     /* CSR not symmetric / sorted / simple             */
+  ND_E_UNSUPPORTED = 3,   /* (r,s) pair or size this build does not handle   */
+  ND_E_OOM = 4,           /* device allocation failed or memory limit hit    */
+  ND_E_OVERFLOW = 5,      /* a 32-bit count or id would overflow             */
+  ND_E_DEVICE = 6,        /* a HIP runtime call failed                       */
+  ND_E_WATCHDOG = 7,      /* a device loop exceeded its iteration bound      */
+  ND_E_STATE = 8,         /* call out of order (e.g. no graph loaded)        */
+  ND_E_CANCELLED = 9      /* the host cancelled the request                  */
+} nd_status;
+
+typedef enum nd_mem {
+  ND_MEM_HOST = 0,        /* pointer is ordinary host memory                 */
+  ND_MEM_DEVICE = 1       /* pointer is device memory of the context's GPU   */
+} nd_mem;
+
+typedef struct nd_ctx nd_ctx;
+
+typedef struct nd_options {
+  int device;             /* HIP device ordinal                               */
+  void *hip_stream;       /* hipStream_t to order work on; NULL = null stream */
+  int validate;           /* nonzero: check the CSR on the device             */
+  uint64_t mem_limit;     /* max bytes of device workspace; 0 = no limit      */
+  uint32_t peel_blocks;   /* workgroups of the persistent peel launch; 0=auto */
+  uint32_t work_chunk;    /* probe elements per lane task (>=1); 0 = auto     */
+  uint64_t watchdog;      /* max peel rounds before ND_E_WATCHDOG; 0 = auto   */
+} nd_options;
+
+/* Per-decomposition statistics. Counters are totals over the whole run. */
+typedef struct nd_info {
+  uint32_t n, r, s;
+  uint64_t m;             /* undirected edges                                 */
+  uint64_t n_r;           /* r-cliques                                        */
+  uint64_t n_s;           /* s-cliques                                        */
+  uint32_t k;             /* maximum core number                              */
+  uint32_t rounds;        /* peeling rounds executed                          */
+  uint64_t n_int;         /* internal nodes of the canonical tree             */
+  uint64_t visits;        /* (r-clique, s-clique) pairs traversed while peeling */
+  uint64_t decrements;    /* count decrements                                 */
+  uint64_t links;         /* link calls (Algorithm 5), cascades included      */
+  uint64_t unites;        /* successful union-find unions                     */
+  uint64_t bucket_scans;  /* scans of the remaining r-cliques for a new k     */
+  uint32_t max_outdeg;    /* out-degree bound reached by the orientation      */
+  uint32_t orient_rounds; /* rounds of the orientation                        */
+  float ms_prep;          /* device time: validation, ids, orientation, tables */
+  float ms_count;         /* device time: s-clique counting                   */
+  float ms_peel;          /* device time: peel + link rounds                  */
+  float ms_tree;          /* device time: tree construction + canonical form  */
+  uint64_t device_bytes;  /* workspace bytes held by the context              */
+} nd_info;
+
+/* Create a context on opt->device (opt may be NULL: device 0, null stream,
+ * validation on). The context owns every device buffer it allocates. */
+nd_status nd_create(nd_ctx **out, const nd_options *opt);
+void nd_destroy(nd_ctx *ctx);
+
+/* Copy a CSR graph into the context. row_ptr: uint64[n+1] with row_ptr[0]=0
+ * and row_ptr[n]=nnz; col: uint32[nnz], rows sorted ascending, symmetric, no
+ * self-loops or duplicates (a simple undirected graph, Section 3); nnz = 2m.
+ * `where` tells whether both pointers are host or device memory. The caller
+ * keeps ownership. Structural errors are reported here when validation is on
+ * (this call then waits for the device). */
+nd_status nd_load_csr(nd_ctx *ctx, uint32_t n, uint64_t nnz, const uint64_t *row_ptr,
+                      const uint32_t *col, nd_mem where);
+
+/* Choose (r,s): supported pairs are (1,2), (2,3), (3,4), (1,3), (2,4), (1,4).
+ * Other 1 <= r < s pairs return ND_E_UNSUPPORTED; r >= s returns
+ * ND_E_INVALID_ARG. */
+nd_status nd_set_rs(nd_ctx *ctx, uint32_t r, uint32_t s);
+
+/* Run the whole pipeline on the context's stream: orientation, r-clique
+ * tables, s-clique counting, peel rounds with linking, tree construction and
+ * canonical numbering. Blocks once on a small readback of the r-clique count
+ * (needed to size the per-r-clique arrays) and at the end; results stay on
+ * the device until read with nd_get_*. */
+nd_status nd_decompose(nd_ctx *ctx);
+
+/* Wait for the context's stream and report device-side errors. */
+nd_status nd_sync(nd_ctx *ctx);
+
+nd_status nd_get_info(nd_ctx *ctx, nd_info *out);
+
+/* r-cliques: n_r * r uint32 vertex ids, each tuple ascending, tuples in
+ * lexicographic order (this order defines the r-clique index). */
+nd_status nd_get_rcliques(nd_ctx *ctx, uint32_t *out, nd_mem where);
+
+/* s-clique degree of every r-clique before peeling: uint32[n_r]. */
+nd_status nd_get_counts(nd_ctx *ctx, uint32_t *out, nd_mem where);
+
+/* Core numbers: uint32[n_r], indexed by r-clique index. */
+nd_status nd_get_coreness(nd_ctx *ctx, uint32_t *out, nd_mem where);
+
+/* Canonical tree: parent uint64[n_r + n_int] (UINT64_MAX for roots) and
+ * level uint32[n_int] (level of node n_r + i). Either pointer may be NULL. */
+nd_status nd_get_tree(nd_ctx *ctx, uint64_t *parent, uint32_t *level, nd_mem where);
+
+const char *nd_status_str(nd_status st);
+
+/* Message of the last error of this context (empty string if none). */
+const char *nd_last_error(const nd_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NUCLEUS_H */

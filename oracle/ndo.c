@@ -101,6 +101,54 @@ int ndo_validate_csr(uint32_t n, const uint64_t *row_ptr, const uint32_t *col) {
 
 /* ---- clique listing by depth-first search over forward neighbours ------- */
 
+/* out = the elements of the sorted list a[0..na) that are neighbours of v,
+ * ascending. Three equivalent ways, whichever touches the fewest entries: a
+ * linear merge of a with the sorted row of v, a binary search of the row for
+ * each element of a, or a binary search of a for each entry of the row. */
+static uint64_t lower_bound32(const uint32_t *a, uint64_t lo, uint64_t hi, uint32_t x) {
+  while (lo < hi) {
+    uint64_t mid = lo + (hi - lo) / 2;
+    if (a[mid] < x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+static uint64_t log2ceil(uint64_t x) {
+  uint64_t lg = 1;
+  while ((1ull << lg) < x) lg++;
+  return lg;
+}
+
+static uint64_t intersect_row(const graph *g, const uint32_t *a, uint64_t na, uint32_t v,
+                              uint32_t *out) {
+  uint64_t b = g->rp[v], be = g->rp[v + 1], k = 0;
+  uint64_t deg = be - b;
+  uint64_t c_merge = na + deg;
+  uint64_t c_probe_a = na * log2ceil(deg);
+  uint64_t c_probe_row = deg * log2ceil(na);
+  if (c_probe_a <= c_merge && c_probe_a <= c_probe_row) {
+    for (uint64_t i = 0; i < na; i++)
+      if (adjacent(g, v, a[i])) out[k++] = a[i];
+    return k;
+  }
+  if (c_probe_row < c_merge) {
+    for (uint64_t j = b; j < be; j++) {
+      uint32_t y = g->col[j];
+      uint64_t p = lower_bound32(a, 0, na, y);
+      if (p < na && a[p] == y) out[k++] = y;
+    }
+    return k;
+  }
+  uint64_t i = 0;
+  while (i < na && b < be) {
+    uint32_t x = a[i], y = g->col[b];
+    if (x == y) { out[k++] = x; i++; b++; }
+    else if (x < y) i++;
+    else b++;
+  }
+  return k;
+}
+
 /* Lists every q-clique once as an ascending tuple, in lexicographic order:
  * tuple[0] runs over all vertices; tuple[d+1] runs over the common
  * neighbours of tuple[0..d] that are larger than tuple[d]. */
@@ -122,17 +170,9 @@ static void lister_rec(lister *L, uint32_t d) {
   for (uint64_t i = 0; i < L->ncand[d]; i++) {
     uint32_t v = L->cand[d][i];
     L->tuple[d] = v;
-    if (d + 1 < L->q) {
-      /* cand[d+1] = cand[d][i+1..] intersected with N(v) (both sorted) */
-      uint64_t a = i + 1, b = g->rp[v], be = g->rp[v + 1], k = 0;
-      while (a < L->ncand[d] && b < be) {
-        uint32_t x = L->cand[d][a], y = g->col[b];
-        if (x == y) { L->cand[d + 1][k++] = x; a++; b++; }
-        else if (x < y) a++;
-        else b++;
-      }
-      L->ncand[d + 1] = k;
-    }
+    if (d + 1 < L->q)
+      L->ncand[d + 1] = intersect_row(g, L->cand[d] + i + 1, L->ncand[d] - i - 1, v,
+                                      L->cand[d + 1]);
     lister_rec(L, d + 1);
   }
 }
@@ -164,7 +204,8 @@ static int list_cliques(const graph *g, uint32_t q, emit_fn emit, void *ctx) {
 typedef struct {
   uint32_t r;
   uint64_t n_r;
-  uint32_t *t;   /* n_r * r, lexicographic */
+  uint32_t *t;       /* n_r * r, lexicographic */
+  uint64_t *first;   /* n+1: tuples starting with vertex a are [first[a], first[a+1]) */
 } rtable;
 
 typedef struct { vec32 v; uint32_t r; } rcollect;
@@ -182,10 +223,11 @@ static int tuple_cmp(const uint32_t *a, const uint32_t *b, uint32_t r) {
   return 0;
 }
 
-/* id of an ascending r-tuple, or NONE if it is not an r-clique */
+/* id of an ascending r-tuple, or NONE if it is not an r-clique: binary
+ * search among the tuples that start with tuple[0] */
 static uint64_t rlookup(const rtable *T, const uint32_t *tuple) {
   if (T->r == 1) return tuple[0];
-  uint64_t lo = 0, hi = T->n_r;
+  uint64_t lo = T->first[tuple[0]], hi = T->first[tuple[0] + 1];
   while (lo < hi) {
     uint64_t mid = lo + (hi - lo) / 2;
     int c = tuple_cmp(T->t + mid * T->r, tuple, T->r);
@@ -231,16 +273,9 @@ static void sscan_rec(sscan *X, uint32_t d) {
   for (uint64_t i = 0; i < X->ncand[d]; i++) {
     uint32_t v = X->cand[d][i];
     X->ext[d] = v;
-    if (d + 1 < q) {
-      uint64_t a = i + 1, b = g->rp[v], be = g->rp[v + 1], k = 0;
-      while (a < X->ncand[d] && b < be) {
-        uint32_t x = X->cand[d][a], y = g->col[b];
-        if (x == y) { X->cand[d + 1][k++] = x; a++; b++; }
-        else if (x < y) a++;
-        else b++;
-      }
-      X->ncand[d + 1] = k;
-    }
+    if (d + 1 < q)
+      X->ncand[d + 1] = intersect_row(g, X->cand[d] + i + 1, X->ncand[d] - i - 1, v,
+                                      X->cand[d + 1]);
     sscan_rec(X, d + 1);
   }
 }
@@ -248,12 +283,17 @@ static void sscan_rec(sscan *X, uint32_t d) {
 static void for_each_sclique(sscan *X, const uint32_t *R) {
   const graph *g = X->g;
   X->R = R;
-  /* C(R): scan the row of R[0], keep vertices adjacent to all of R[1..] */
+  /* C(R): scan the row of the member of R with the fewest neighbours and
+   * keep the vertices adjacent to every other member */
+  uint32_t base = 0;
+  for (uint32_t t = 1; t < X->r; t++)
+    if (g->rp[R[t] + 1] - g->rp[R[t]] < g->rp[R[base] + 1] - g->rp[R[base]]) base = t;
   uint64_t k = 0;
-  for (uint64_t j = g->rp[R[0]]; j < g->rp[R[0] + 1]; j++) {
+  for (uint64_t j = g->rp[R[base]]; j < g->rp[R[base] + 1]; j++) {
     uint32_t w = g->col[j];
     int ok = 1;
-    for (uint32_t t = 1; t < X->r && ok; t++) ok = adjacent(g, R[t], w);
+    for (uint32_t t = 0; t < X->r && ok; t++)
+      if (t != base) ok = adjacent(g, R[t], w);
     if (ok) X->cand[0][k++] = w;
   }
   X->ncand[0] = k;
@@ -461,8 +501,12 @@ static int do_count(const graph *g, uint32_t r, uint32_t s, ndo_result *out, rta
   out->rcliques = T->t;
   if (!out->rcliques) out->rcliques = (uint32_t *)malloc(sizeof(uint32_t));
   T->t = out->rcliques;
+  T->first = (uint64_t *)calloc((uint64_t)g->n + 1, sizeof(uint64_t));
   out->count = (uint64_t *)calloc(T->n_r ? T->n_r : 1, sizeof(uint64_t));
-  if (!out->count) return NDO_E_OOM;
+  if (!out->count || !T->first) return NDO_E_OOM;
+  /* first[a] = number of tuples whose first vertex is below a */
+  for (uint64_t i = 0; i < T->n_r; i++) T->first[T->t[i * r] + 1]++;
+  for (uint32_t a = 0; a < g->n; a++) T->first[a + 1] += T->first[a];
   counter c;
   memset(&c, 0, sizeof(c));
   c.T = T; c.s = s; c.count = out->count;
@@ -483,7 +527,9 @@ int ndo_count(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
   if (st != NDO_OK) return st;
   out->n = n; out->r = r; out->s = s;
   rtable T;
+  memset(&T, 0, sizeof(T));
   st = do_count(&g, r, s, out, &T);
+  free(T.first);
   if (st != NDO_OK) ndo_free(out);
   return st;
 }
@@ -501,8 +547,9 @@ int ndo_decompose(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
   /* O1 + O2 */
   double t0 = now_s();
   rtable T;
+  memset(&T, 0, sizeof(T));
   st = do_count(&g, r, s, out, &T);
-  if (st != NDO_OK) { ndo_free(out); return st; }
+  if (st != NDO_OK) { free(T.first); ndo_free(out); return st; }
   const uint64_t nr = T.n_r;
   const uint64_t nr1 = nr ? nr : 1;
   double t1 = now_s();
@@ -528,7 +575,7 @@ int ndo_decompose(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
   if (!out->coreness || !out->peel_order || !P.deg || !P.gone || !P.vert || !P.pos ||
       !P.bin || sst != NDO_OK) {
     free(P.deg); free(P.gone); free(P.vert); free(P.pos); free(P.bin); sscan_free(&X);
-    ndo_free(out);
+    free(T.first); ndo_free(out);
     return NDO_E_OOM;
   }
   for (uint64_t i = 0; i < nr; i++) { P.deg[i] = out->count[i]; P.bin[P.deg[i]]++; }
@@ -571,7 +618,7 @@ int ndo_decompose(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
   memset(&pieces, 0, sizeof(pieces));
   if (!uf || !stamp || !top || !par || !minleaf || !nlevel) {
     free(uf); free(stamp); free(top); free(par); free(minleaf); free(nlevel); free(active);
-    sscan_free(&X); ndo_free(out);
+    sscan_free(&X); free(T.first); ndo_free(out);
     return NDO_E_OOM;
   }
   memset(active, 0, nr1);
@@ -644,7 +691,7 @@ int ndo_decompose(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
   }
   sscan_free(&X);
   free(pieces.a); free(uf); free(stamp); free(top); free(active);
-  if (oom) { free(par); free(minleaf); free(nlevel); ndo_free(out); return NDO_E_OOM; }
+  if (oom) { free(par); free(minleaf); free(nlevel); free(T.first); ndo_free(out); return NDO_E_OOM; }
 
   /* O5: canonical numbering by (level, min leaf) */
   nodekey *keys = (nodekey *)malloc((nint ? nint : 1) * sizeof(nodekey));
@@ -652,7 +699,7 @@ int ndo_decompose(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
   out->parent = (uint64_t *)malloc((nr + nint ? nr + nint : 1) * sizeof(uint64_t));
   out->level = (uint64_t *)malloc((nint ? nint : 1) * sizeof(uint64_t));
   if (!keys || !canon || !out->parent || !out->level) {
-    free(keys); free(canon); free(par); free(minleaf); free(nlevel); ndo_free(out);
+    free(keys); free(canon); free(par); free(minleaf); free(nlevel); free(T.first); ndo_free(out);
     return NDO_E_OOM;
   }
   for (uint64_t i = 0; i < nint; i++) {
@@ -672,5 +719,6 @@ int ndo_decompose(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
   out->n_int = nint;
   free(keys); free(canon); free(par); free(minleaf); free(nlevel);
   out->t_tree = now_s() - t2;
+  free(T.first);
   return NDO_OK;
 }

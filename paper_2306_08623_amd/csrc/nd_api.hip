@@ -1,0 +1,354 @@
+// nd_api.hip -- the C ABI declared in include/nucleus.h: context, device
+// workspace, the decomposition pipeline and the result getters.
+#include "nd_internal.h"
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+
+nd_status nd_validate_loaded(nd_ctx *c);
+
+nd_status nd_fail(nd_ctx *c, nd_status st, const std::string &msg) {
+  if (c) c->last_error = msg;
+  return st;
+}
+
+nd_status nd_hip(nd_ctx *c, hipError_t e, const char *what) {
+  if (e == hipSuccess) return ND_OK;
+  if (e == hipErrorOutOfMemory)
+    return nd_fail(c, ND_E_OOM, std::string(what) + ": " + hipGetErrorString(e));
+  return nd_fail(c, ND_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void *nd_buf(nd_ctx *c, int id, size_t bytes, nd_status *st) {
+  *st = ND_OK;
+  if ((int)c->bufs.size() < B_COUNT) c->bufs.resize(B_COUNT);
+  DevBuf &b = c->bufs[id];
+  if (bytes == 0) bytes = 8;
+  if (b.p && b.bytes >= bytes) return b.p;
+  size_t want = std::max<size_t>(bytes, b.bytes + b.bytes / 4);   // grow with slack
+  uint64_t held_after = c->bytes_held - b.bytes + want;
+  if (c->mem_limit && held_after > c->mem_limit) {
+    want = bytes;
+    held_after = c->bytes_held - b.bytes + want;
+    if (held_after > c->mem_limit) {
+      *st = nd_fail(c, ND_E_OOM, "device workspace limit reached (" + std::to_string(held_after) +
+                                     " > " + std::to_string(c->mem_limit) + " bytes)");
+      return nullptr;
+    }
+  }
+  if (b.p) {
+    // the old buffer may still be read by queued kernels
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+      *st = nd_hip(c, e, "sync before realloc");
+      return nullptr;
+    }
+    (void)hipFree(b.p);
+    c->bytes_held -= b.bytes;
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *st = nd_fail(c, ND_E_OOM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+    return nullptr;
+  }
+  b.p = p;
+  b.bytes = want;
+  c->bytes_held += want;
+  return p;
+}
+
+static nd_status set_dev(nd_ctx *c) {
+  return nd_hip(c, hipSetDevice(c->device), "hipSetDevice");
+}
+
+extern "C" {
+
+const char *nd_status_str(nd_status st) {
+  switch (st) {
+    case ND_OK: return "ok";
+    case ND_E_INVALID_ARG: return "invalid argument";
+    case ND_E_BAD_GRAPH: return "input is not a simple undirected CSR graph";
+    case ND_E_UNSUPPORTED: return "unsupported";
+    case ND_E_OOM: return "out of device memory";
+    case ND_E_OVERFLOW: return "32-bit overflow";
+    case ND_E_DEVICE: return "HIP runtime error";
+    case ND_E_WATCHDOG: return "device watchdog";
+    case ND_E_STATE: return "call out of order";
+    case ND_E_CANCELLED: return "cancelled";
+  }
+  return "unknown status";
+}
+
+const char *nd_last_error(const nd_ctx *c) { return c ? c->last_error.c_str() : ""; }
+
+nd_status nd_create(nd_ctx **out, const nd_options *opt) {
+  if (!out) return ND_E_INVALID_ARG;
+  *out = nullptr;
+  nd_ctx *c = new (std::nothrow) nd_ctx();
+  if (!c) return ND_E_OOM;
+  if (opt) {
+    c->device = opt->device;
+    c->stream = (hipStream_t)opt->hip_stream;
+    c->validate = opt->validate;
+    c->mem_limit = opt->mem_limit;
+    c->peel_blocks = opt->peel_blocks;
+    c->work_chunk = opt->work_chunk;
+    c->watchdog = opt->watchdog;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    delete c;
+    return ND_E_DEVICE;
+  }
+  if (c->device < 0 || c->device >= ndev) {
+    delete c;
+    return ND_E_INVALID_ARG;
+  }
+  if (set_dev(c) != ND_OK) {
+    delete c;
+    return ND_E_DEVICE;
+  }
+  if (hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, c->device) !=
+          hipSuccess ||
+      c->cu_count <= 0) {
+    delete c;
+    return ND_E_DEVICE;
+  }
+  int coop = 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device) != hipSuccess ||
+      !coop) {
+    delete c;
+    return ND_E_UNSUPPORTED;
+  }
+  c->bufs.resize(B_COUNT);
+  c->events_ok = true;
+  for (int i = 0; i < 6; i++)
+    if (hipEventCreate(&c->ev[i]) != hipSuccess) c->events_ok = false;
+  nd_status st;
+  if (!nd_buf(c, B_SCAL, sizeof(DevScalars), &st)) {
+    nd_destroy(c);
+    return st;
+  }
+  *out = c;
+  return ND_OK;
+}
+
+void nd_destroy(nd_ctx *c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (auto &b : c->bufs)
+    if (b.p) (void)hipFree(b.p);
+  for (int i = 0; i < 6; i++)
+    if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  delete c;
+}
+
+nd_status nd_load_csr(nd_ctx *c, uint32_t n, uint64_t nnz, const uint64_t *row_ptr,
+                      const uint32_t *col, nd_mem where) {
+  if (!c) return ND_E_INVALID_ARG;
+  nd_status st = set_dev(c);
+  if (st != ND_OK) return st;
+  c->have_graph = false;
+  c->decomposed = false;
+  if (!row_ptr || (nnz && !col)) return nd_fail(c, ND_E_INVALID_ARG, "NULL row_ptr or col");
+  if (where != ND_MEM_HOST && where != ND_MEM_DEVICE)
+    return nd_fail(c, ND_E_INVALID_ARG, "bad memory kind");
+  if (n == 0xFFFFFFFFu) return nd_fail(c, ND_E_UNSUPPORTED, "n must be below 2^32-1");
+  if (nnz & 1) return nd_fail(c, ND_E_BAD_GRAPH, "nnz is odd: the CSR cannot be symmetric");
+  if (nnz / 2 >= 0xFFFFFFFFull) return nd_fail(c, ND_E_UNSUPPORTED, "edge ids exceed 32 bits");
+  if (where == ND_MEM_HOST && c->validate) {
+    if (row_ptr[0] != 0 || row_ptr[n] != nnz)
+      return nd_fail(c, ND_E_BAD_GRAPH, "row_ptr[0] must be 0 and row_ptr[n] must equal nnz");
+    for (uint32_t u = 0; u < n; u++)
+      if (row_ptr[u + 1] < row_ptr[u]) return nd_fail(c, ND_E_BAD_GRAPH, "row_ptr decreases");
+  }
+  uint64_t *rp = (uint64_t *)nd_buf(c, B_RP, (n + 1ull) * 8, &st);
+  if (!rp) return st;
+  uint32_t *dcol = (uint32_t *)nd_buf(c, B_COL, std::max<uint64_t>(nnz, 1) * 4, &st);
+  if (!dcol) return st;
+  hipMemcpyKind kind = where == ND_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  if ((st = nd_hip(c, hipMemcpyAsync(rp, row_ptr, (n + 1ull) * 8, kind, c->stream), "copy row_ptr")) !=
+      ND_OK)
+    return st;
+  if (nnz &&
+      (st = nd_hip(c, hipMemcpyAsync(dcol, col, nnz * 4, kind, c->stream), "copy col")) != ND_OK)
+    return st;
+  c->n = n;
+  c->nnz = nnz;
+  c->m = nnz / 2;
+  if (c->validate) {
+    st = nd_validate_loaded(c);
+    if (st != ND_OK) return st;
+  }
+  c->have_graph = true;
+  return ND_OK;
+}
+
+nd_status nd_set_rs(nd_ctx *c, uint32_t r, uint32_t s) {
+  if (!c) return ND_E_INVALID_ARG;
+  if (r < 1 || s <= r) return nd_fail(c, ND_E_INVALID_ARG, "need 1 <= r < s");
+  bool ok = (r == 1 && s == 2) || (r == 2 && s == 3) || (r == 3 && s == 4);
+  if (!ok) return nd_fail(c, ND_E_UNSUPPORTED, "this (r,s) pair is not built");
+  c->r = r;
+  c->s = s;
+  c->decomposed = false;
+  return ND_OK;
+}
+
+static nd_status check_device_status(nd_ctx *c, DevScalars *host) {
+  DevScalars *sc = (DevScalars *)c->bufs[B_SCAL].p;
+  nd_status st = nd_hip(
+      c, hipMemcpyAsync(host, sc, sizeof(DevScalars), hipMemcpyDeviceToHost, c->stream),
+      "scalars readback");
+  if (st != ND_OK) return st;
+  st = nd_hip(c, hipStreamSynchronize(c->stream), "stream sync");
+  if (st != ND_OK) return st;
+  if (host->status & ND_DERR_WATCHDOG)
+    return nd_fail(c, ND_E_WATCHDOG, "a device loop exceeded its bound");
+  if (host->status & ND_DERR_LINKQ)
+    return nd_fail(c, ND_E_OOM, "link spill queue overflowed");
+  if (host->status & ND_DERR_OVERFLOW)
+    return nd_fail(c, ND_E_UNSUPPORTED, "an oriented out-neighbourhood exceeds the listing buffer");
+  if (host->status & ND_DERR_BADGRAPH) return nd_fail(c, ND_E_BAD_GRAPH, "bad graph");
+  return ND_OK;
+}
+
+nd_status nd_decompose(nd_ctx *c) {
+  if (!c) return ND_E_INVALID_ARG;
+  nd_status st = set_dev(c);
+  if (st != ND_OK) return st;
+  if (!c->have_graph) return nd_fail(c, ND_E_STATE, "no graph loaded");
+  if (!c->r) return nd_fail(c, ND_E_STATE, "r and s not set");
+  c->decomposed = false;
+  c->last_error.clear();
+  memset(&c->info, 0, sizeof(c->info));
+  DevScalars *sc = (DevScalars *)c->bufs[B_SCAL].p;
+  if ((st = nd_hip(c, hipMemsetAsync(sc, 0, sizeof(DevScalars), c->stream), "scalars")) != ND_OK)
+    return st;
+  if (c->events_ok) (void)hipEventRecord(c->ev[0], c->stream);
+  GraphView gv;
+  memset(&gv, 0, sizeof(gv));
+  if ((st = nd_stage_prep(c, &gv)) != ND_OK) return st;
+  if (c->events_ok) (void)hipEventRecord(c->ev[1], c->stream);
+  if ((st = nd_stage_count(c, gv)) != ND_OK) return st;
+  if (c->events_ok) (void)hipEventRecord(c->ev[2], c->stream);
+  DevScalars hs;
+  if ((st = check_device_status(c, &hs)) != ND_OK) return st;
+  c->info.n_s = hs.n_s;
+  c->info.max_outdeg = hs.max_outdeg;
+  if ((st = nd_stage_peel(c, gv)) != ND_OK) return st;
+  if (c->events_ok) (void)hipEventRecord(c->ev[3], c->stream);
+  if ((st = check_device_status(c, &hs)) != ND_OK) return st;
+  if ((st = nd_stage_tree(c, gv)) != ND_OK) return st;
+  if (c->events_ok) (void)hipEventRecord(c->ev[4], c->stream);
+  if ((st = check_device_status(c, &hs)) != ND_OK) return st;
+  c->gv = gv;
+  nd_info &I = c->info;
+  I.n = c->n;
+  I.r = c->r;
+  I.s = c->s;
+  I.m = c->m;
+  I.n_r = c->n_r;
+  I.k = c->n_r ? hs.k : 0;
+  I.rounds = hs.rounds;
+  I.n_int = c->n_int;
+  I.visits = hs.visits;
+  I.decrements = hs.decrements;
+  I.links = hs.links;
+  I.unites = hs.unites;
+  I.bucket_scans = hs.bucket_scans;
+  I.orient_rounds = hs.orient_round;
+  I.device_bytes = c->bytes_held;
+  if (c->events_ok) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) I.ms_prep = ms;
+    if (hipEventElapsedTime(&ms, c->ev[1], c->ev[2]) == hipSuccess) I.ms_count = ms;
+    if (hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) I.ms_peel = ms;
+    if (hipEventElapsedTime(&ms, c->ev[3], c->ev[4]) == hipSuccess) I.ms_tree = ms;
+    (void)hipGetLastError();
+  }
+  c->decomposed = true;
+  return ND_OK;
+}
+
+nd_status nd_sync(nd_ctx *c) {
+  if (!c) return ND_E_INVALID_ARG;
+  nd_status st = set_dev(c);
+  if (st != ND_OK) return st;
+  DevScalars hs;
+  return check_device_status(c, &hs);
+}
+
+nd_status nd_get_info(nd_ctx *c, nd_info *out) {
+  if (!c || !out) return ND_E_INVALID_ARG;
+  if (!c->decomposed) return nd_fail(c, ND_E_STATE, "no decomposition result");
+  *out = c->info;
+  return ND_OK;
+}
+
+static nd_status copy_out(nd_ctx *c, void *dst, const void *src, size_t bytes, nd_mem where) {
+  if (bytes == 0) return ND_OK;
+  if (where != ND_MEM_HOST && where != ND_MEM_DEVICE)
+    return nd_fail(c, ND_E_INVALID_ARG, "bad memory kind");
+  hipMemcpyKind kind = where == ND_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+  nd_status st = nd_hip(c, hipMemcpyAsync(dst, src, bytes, kind, c->stream), "copy out");
+  if (st != ND_OK) return st;
+  return nd_hip(c, hipStreamSynchronize(c->stream), "copy out sync");
+}
+
+nd_status nd_get_rcliques(nd_ctx *c, uint32_t *out, nd_mem where) {
+  if (!c || (!out && c->n_r)) return ND_E_INVALID_ARG;
+  nd_status st = set_dev(c);
+  if (st != ND_OK) return st;
+  if (!c->decomposed) return nd_fail(c, ND_E_STATE, "no decomposition result");
+  const size_t bytes = c->n_r * c->r * 4ull;
+  if (bytes == 0) return ND_OK;
+  if (where == ND_MEM_DEVICE) {
+    if ((st = nd_write_rcliques(c, c->gv, out)) != ND_OK) return st;
+    return nd_hip(c, hipStreamSynchronize(c->stream), "rcliques sync");
+  }
+  uint32_t *tmp = (uint32_t *)nd_buf(c, B_RCL, bytes, &st);
+  if (!tmp) return st;
+  if ((st = nd_write_rcliques(c, c->gv, tmp)) != ND_OK) return st;
+  return copy_out(c, out, tmp, bytes, where);
+}
+
+nd_status nd_get_counts(nd_ctx *c, uint32_t *out, nd_mem where) {
+  if (!c || (!out && c->n_r)) return ND_E_INVALID_ARG;
+  nd_status st = set_dev(c);
+  if (st != ND_OK) return st;
+  if (!c->decomposed) return nd_fail(c, ND_E_STATE, "no decomposition result");
+  return copy_out(c, out, c->bufs[B_CNT0].p, c->n_r * 4ull, where);
+}
+
+nd_status nd_get_coreness(nd_ctx *c, uint32_t *out, nd_mem where) {
+  if (!c || (!out && c->n_r)) return ND_E_INVALID_ARG;
+  nd_status st = set_dev(c);
+  if (st != ND_OK) return st;
+  if (!c->decomposed) return nd_fail(c, ND_E_STATE, "no decomposition result");
+  return copy_out(c, out, c->bufs[B_CNT].p, c->n_r * 4ull, where);
+}
+
+nd_status nd_get_tree(nd_ctx *c, uint64_t *parent, uint32_t *level, nd_mem where) {
+  if (!c) return ND_E_INVALID_ARG;
+  nd_status st = set_dev(c);
+  if (st != ND_OK) return st;
+  if (!c->decomposed) return nd_fail(c, ND_E_STATE, "no decomposition result");
+  if (c->n_r == 0) return ND_OK;
+  if (parent && (st = copy_out(c, parent, c->bufs[B_PARENT].p, (c->n_r + c->n_int) * 8ull,
+                               where)) != ND_OK)
+    return st;
+  if (level && c->n_int &&
+      (st = copy_out(c, level, c->bufs[B_LEVEL].p, c->n_int * 4ull, where)) != ND_OK)
+    return st;
+  return ND_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,232 @@
+// nd_count.hip -- s-clique counting per r-clique (Algorithm 3: the s-clique
+// counts stored per r-clique before peeling starts).
+//
+// Every s-clique is listed exactly once in the oriented graph DG, from its
+// two lowest vertices u -> v (Section 3 low out-degree orientation; the
+// recursive listing of Algorithm 3's counting step): the remaining s-2
+// vertices are common out-neighbours of u and v. For each listed s-clique
+// the kernel resolves the ids of its C(s,r) r-cliques and adds one to each
+// count with an atomic.
+//
+//   s = 2: the count of a vertex is its degree.
+//   s = 3: one lane per DG edge u -> v; every common out-neighbour w is a
+//          triangle {u, v, w}; edge ids come from the DG slots.
+//   s = 4: one wave per DG edge; the common out-neighbourhood C2 is built in
+//          LDS (ballot compaction keeps it ascending); lanes then test the
+//          pairs {w, x} of C2 for adjacency; every adjacent pair closes a
+//          4-clique {u, v, w, x}. Triangle ids (r = 3) are read from W(e) of
+//          the triangle's lexicographically first edge by binary search.
+#include "nd_internal.h"
+
+#include <algorithm>
+
+namespace {
+
+constexpr uint32_t kCountBlock = 256;
+constexpr uint32_t kC2Cap = 1024;   // LDS capacity per wave for C2 (entries)
+
+__global__ void k_count_degree(uint32_t n, const uint64_t *__restrict__ rp,
+                               uint32_t *__restrict__ cnt) {
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+    cnt[v] = (uint32_t)(rp[v + 1] - rp[v]);
+}
+
+// triangle id of {a, b, c} given the ids of its three edges, via W of the
+// edge joining the two smallest vertices
+__device__ __forceinline__ uint32_t tri_lookup(const GraphView &g, uint32_t a, uint32_t b,
+                                               uint32_t c, uint32_t e_ab, uint32_t e_ac,
+                                               uint32_t e_bc) {
+  // sort (a,b,c) ascending, carrying the edge opposite each vertex
+  // opposite(a) = e_bc, opposite(b) = e_ac, opposite(c) = e_ab
+  uint32_t x0 = a, x1 = b, x2 = c;
+  uint32_t o0 = e_bc, o1 = e_ac, o2 = e_ab;
+  if (x0 > x1) { uint32_t t = x0; x0 = x1; x1 = t; t = o0; o0 = o1; o1 = t; }
+  if (x1 > x2) { uint32_t t = x1; x1 = x2; x2 = t; t = o1; o1 = o2; o2 = t; }
+  if (x0 > x1) { uint32_t t = x0; x0 = x1; x1 = t; t = o0; o0 = o1; o1 = t; }
+  // first edge {x0, x1} is opposite x2
+  const uint64_t b0 = g.wp[o2], b1 = g.wp[o2 + 1];
+  uint64_t p = lower_bound_u32<uint64_t>(g.wc, b0, b1, x2);
+  if (p == b1 || g.wc[p] != x2) return ND_NONE;   // impossible for a real triangle
+  return g.wt[p];
+}
+
+template <int R>
+__global__ void __launch_bounds__(kCountBlock) k_count_s3(GraphView g, uint32_t *__restrict__ cnt,
+                                                          DevScalars *sc) {
+  uint64_t local = 0;
+  for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < g.m;
+       j += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t u = segment_of(g.dgp, g.n, j);
+    const uint32_t v = g.dgc[j];
+    const uint32_t e_uv = g.dge[j];
+    uint64_t bu = g.dgp[u], eu = g.dgp[u + 1], bv = g.dgp[v], ev = g.dgp[v + 1];
+    uint64_t lo = bv;
+    for (uint64_t i = bu; i < eu && lo < ev; i++) {
+      const uint32_t w = g.dgc[i];
+      lo = lower_bound_u32<uint64_t>(g.dgc, lo, ev, w);
+      if (lo < ev && g.dgc[lo] == w) {
+        local++;
+        if (R == 1) {
+          atomicAdd(&cnt[u], 1u);
+          atomicAdd(&cnt[v], 1u);
+          atomicAdd(&cnt[w], 1u);
+        } else {
+          atomicAdd(&cnt[e_uv], 1u);
+          atomicAdd(&cnt[g.dge[i]], 1u);
+          atomicAdd(&cnt[g.dge[lo]], 1u);
+        }
+      }
+    }
+  }
+  local = wave_sum64(local);
+  if (lane_id() == 0 && local) atomicAdd((unsigned long long *)&sc->n_s, (unsigned long long)local);
+}
+
+template <int R>
+__global__ void __launch_bounds__(kCountBlock) k_count_s4(GraphView g, uint32_t *__restrict__ cnt,
+                                                          DevScalars *sc) {
+  constexpr uint32_t W = kCountBlock / 64;
+  __shared__ uint32_t s_v[W][kC2Cap];
+  __shared__ uint32_t s_eu[W][kC2Cap];
+  __shared__ uint32_t s_ev[W][kC2Cap];
+  const uint32_t wv = threadIdx.x / 64;
+  const uint32_t lane = lane_id();
+  uint32_t *cv = s_v[wv];
+  uint32_t *ceu = s_eu[wv];
+  uint32_t *cev = s_ev[wv];
+  uint64_t local = 0;
+  const uint64_t nwaves = (uint64_t)gridDim.x * W;
+  for (uint64_t j = blockIdx.x * (uint64_t)W + wv; j < g.m; j += nwaves) {
+    const uint32_t u = segment_of(g.dgp, g.n, j);
+    const uint32_t v = g.dgc[j];
+    const uint32_t e_uv = g.dge[j];
+    const uint64_t bu = g.dgp[u], eu = g.dgp[u + 1], bv = g.dgp[v], ev = g.dgp[v + 1];
+    // C2 = N+(u) intersect N+(v), ascending, with the edge ids to u and v
+    uint32_t c = 0;
+    for (uint64_t base = bu; base < eu; base += 64) {
+      const uint64_t i = base + lane;
+      bool hit = false;
+      uint32_t w = 0, e_uw = 0, e_vw = 0;
+      if (i < eu) {
+        w = g.dgc[i];
+        uint64_t p = find_u32<uint64_t>(g.dgc, bv, ev, w);
+        if (p < ev) {
+          hit = true;
+          e_uw = g.dge[i];
+          e_vw = g.dge[p];
+        }
+      }
+      uint64_t mask = ballot64(hit);
+      if (hit) {
+        uint64_t below = mask & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)));
+        uint32_t slot = c + __popcll(below);
+        if (slot < kC2Cap) {
+          cv[slot] = w;
+          ceu[slot] = e_uw;
+          cev[slot] = e_vw;
+        }
+      }
+      c += __popcll(mask);
+    }
+    if (c > kC2Cap) {   // the host sizes launches so this cannot happen
+      if (lane == 0) atomicOr(&sc->status, ND_DERR_OVERFLOW);
+      continue;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    // pairs {cv[a], cv[b]}, a < b
+    for (uint32_t a = 0; a + 1 < c; a++) {
+      const uint32_t w = cv[a];
+      const uint64_t kw = g.okey[w];
+      for (uint32_t b = a + 1 + lane; b < c; b += 64) {
+        const uint32_t x = cv[b];
+        // adjacency of w and x through the out-row of the lower-key vertex
+        uint32_t lowv = w, highv = x;
+        if (g.okey[x] < kw) { lowv = x; highv = w; }
+        const uint64_t bl = g.dgp[lowv], el = g.dgp[lowv + 1];
+        const uint64_t p = find_u32<uint64_t>(g.dgc, bl, el, highv);
+        if (p == el) continue;
+        local++;
+        if (R == 1) {
+          atomicAdd(&cnt[u], 1u);
+          atomicAdd(&cnt[v], 1u);
+          atomicAdd(&cnt[w], 1u);
+          atomicAdd(&cnt[x], 1u);
+        } else if (R == 2) {
+          atomicAdd(&cnt[e_uv], 1u);
+          atomicAdd(&cnt[ceu[a]], 1u);
+          atomicAdd(&cnt[cev[a]], 1u);
+          atomicAdd(&cnt[ceu[b]], 1u);
+          atomicAdd(&cnt[cev[b]], 1u);
+          atomicAdd(&cnt[g.dge[p]], 1u);
+        } else {
+          const uint32_t e_wx = g.dge[p];
+          // triangles {u,v,w} {u,v,x} {u,w,x} {v,w,x}
+          const uint32_t t4[4] = {tri_lookup(g, u, v, w, e_uv, ceu[a], cev[a]),
+                                  tri_lookup(g, u, v, x, e_uv, ceu[b], cev[b]),
+                                  tri_lookup(g, u, w, x, ceu[a], ceu[b], e_wx),
+                                  tri_lookup(g, v, w, x, cev[a], cev[b], e_wx)};
+#pragma unroll
+          for (int z = 0; z < 4; z++) {
+            if (t4[z] == ND_NONE) atomicOr(&sc->status, ND_DERR_BADGRAPH);
+            else atomicAdd(&cnt[t4[z]], 1u);
+          }
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  local = wave_sum64(local);
+  if (lane == 0 && local) atomicAdd((unsigned long long *)&sc->n_s, (unsigned long long)local);
+}
+
+}  // namespace
+
+nd_status nd_stage_count(nd_ctx *c, const GraphView &g) {
+  nd_status st;
+  DevScalars *sc = (DevScalars *)c->bufs[B_SCAL].p;
+  const uint64_t nr = c->n_r;
+  uint32_t *cnt = (uint32_t *)nd_buf(c, B_CNT, std::max<uint64_t>(nr, 1) * 4, &st);
+  if (!cnt) return st;
+  uint32_t *cnt0 = (uint32_t *)nd_buf(c, B_CNT0, std::max<uint64_t>(nr, 1) * 4, &st);
+  if (!cnt0) return st;
+  st = nd_hip(c, hipMemsetAsync(&sc->n_s, 0, 8, c->stream), "memset n_s");
+  if (st != ND_OK) return st;
+  if (nr) {
+    st = nd_hip(c, hipMemsetAsync(cnt, 0, nr * 4, c->stream), "memset cnt");
+    if (st != ND_OK) return st;
+  }
+  const uint32_t r = c->r, s = c->s;
+  if (s == 2) {
+    if (g.n)
+      hipLaunchKernelGGL(k_count_degree, dim3(nd_grid(g.n, 256, 8192)), dim3(256), 0, c->stream,
+                         g.n, g.rp, cnt);
+    uint64_t ns = g.m;
+    st = nd_hip(c, hipMemcpyAsync(&sc->n_s, &ns, 8, hipMemcpyHostToDevice, c->stream), "n_s");
+    if (st != ND_OK) return st;
+  } else if (s == 3 && g.m) {
+    const uint32_t grid = nd_grid(g.m, kCountBlock, 16384);
+    if (r == 1)
+      hipLaunchKernelGGL(k_count_s3<1>, dim3(grid), dim3(kCountBlock), 0, c->stream, g, cnt, sc);
+    else
+      hipLaunchKernelGGL(k_count_s3<2>, dim3(grid), dim3(kCountBlock), 0, c->stream, g, cnt, sc);
+  } else if (s == 4 && g.m) {
+    // C2 fits the LDS buffer whenever the maximum out-degree does
+    if (c->info.max_outdeg > kC2Cap)
+      return nd_fail(c, ND_E_UNSUPPORTED,
+                     "oriented out-degree exceeds the 4-clique listing buffer (1024)");
+    const uint32_t grid = nd_grid(g.m, kCountBlock / 64, 65536);
+    if (r == 1)
+      hipLaunchKernelGGL(k_count_s4<1>, dim3(grid), dim3(kCountBlock), 0, c->stream, g, cnt, sc);
+    else if (r == 2)
+      hipLaunchKernelGGL(k_count_s4<2>, dim3(grid), dim3(kCountBlock), 0, c->stream, g, cnt, sc);
+    else
+      hipLaunchKernelGGL(k_count_s4<3>, dim3(grid), dim3(kCountBlock), 0, c->stream, g, cnt, sc);
+  }
+  st = nd_hip(c, hipGetLastError(), "count kernels");
+  if (st != ND_OK) return st;
+  if (nr)
+    st = nd_hip(c, hipMemcpyAsync(cnt0, cnt, nr * 4, hipMemcpyDeviceToDevice, c->stream),
+                "copy counts");
+  return st;
+}

@@ -1,0 +1,275 @@
+// nd_internal.h -- shared declarations of the gfx950 nucleus decomposition
+// library: device views of the graph tables, device helpers, and the host
+// context. Only the library's own .hip files include this header.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/nucleus.h"
+
+#define ND_NONE 0xFFFFFFFFu          // empty r-clique id / empty L entry
+#define ND_ALIVE 0xFFFFFFFFu         // peel_round of an unpeeled r-clique
+#define ND_NONE64 0xFFFFFFFFFFFFFFFFull
+
+// error codes written by kernels into the device status word
+#define ND_DERR_WATCHDOG 1u
+#define ND_DERR_LINKQ 2u
+#define ND_DERR_BADGRAPH 4u
+#define ND_DERR_OVERFLOW 8u
+
+// ---------------------------------------------------------------------------
+// Device views (plain pointers, passed by value to kernels)
+// ---------------------------------------------------------------------------
+
+// Undirected CSR plus per-slot edge ids and the oriented out-CSR (DG).
+struct GraphView {
+  uint32_t n;
+  uint64_t nnz;              // 2m
+  uint64_t m;
+  const uint64_t *rp;        // [n+1]
+  const uint32_t *col;       // [nnz], rows ascending
+  const uint32_t *eid;       // [nnz] id of the undirected edge in each slot
+  const uint32_t *eu;        // [m] smaller endpoint of edge id
+  const uint32_t *ev;        // [m] larger endpoint
+  const uint64_t *okey;      // [n] orientation key: u -> v is an out-edge iff okey[u] < okey[v]
+  const uint64_t *dgp;       // [n+1] oriented out-CSR offsets
+  const uint32_t *dgc;       // [m] out-neighbours, ascending vertex id
+  const uint32_t *dge;       // [m] edge id of each out-slot
+  // edge -> triangle lists (only for r = 3)
+  const uint64_t *wp;        // [m+1] offsets of W(e), the common neighbours of e
+  const uint32_t *wc;        // [3 n_tri] W entries (third vertex), ascending per edge
+  const uint32_t *wt;        // [3 n_tri] triangle id of each W entry
+  const uint32_t *te;        // [3 n_tri] (e_ab, e_ac, e_bc) of triangle (a<b<c)
+};
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+
+// Coherent (agent-scope) relaxed atomics. Plain loads may hit a stale line in
+// another XCD's L2; these go to the coherence point.
+__device__ __forceinline__ uint32_t ld_acq32(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_acq64(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool cas32(uint32_t *p, uint32_t expect, uint32_t desired) {
+  return __hip_atomic_compare_exchange_strong(p, &expect, desired, __ATOMIC_RELAXED,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// First index in [lo, hi) of a sorted array whose value is >= x.
+template <typename IdxT>
+__device__ __forceinline__ IdxT lower_bound_u32(const uint32_t *a, IdxT lo, IdxT hi, uint32_t x) {
+  while (lo < hi) {
+    IdxT mid = lo + ((hi - lo) >> 1);
+    if (a[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Index of x in the sorted range a[lo, hi), or hi when absent.
+template <typename IdxT>
+__device__ __forceinline__ IdxT find_u32(const uint32_t *a, IdxT lo, IdxT hi, uint32_t x) {
+  IdxT p = lower_bound_u32<IdxT>(a, lo, hi, x);
+  return (p < hi && a[p] == x) ? p : hi;
+}
+
+// Last index i in [0, n) with a[i] <= x for a non-decreasing u64 array whose
+// first element is <= x (segment search over exclusive offsets).
+__device__ __forceinline__ uint32_t segment_of(const uint64_t *a, uint32_t n, uint64_t x) {
+  uint32_t lo = 0, hi = n;   // invariant: a[lo] <= x, answer in [lo, hi)
+  while (hi - lo > 1) {
+    uint32_t mid = lo + ((hi - lo) >> 1);
+    if (a[mid] <= x) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
+
+__device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
+
+// Wave-wide inclusive prefix sum of a 32-bit value (wave64).
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t t = __shfl_up(v, d, 64);
+    if (lane >= (uint32_t)d) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_min32(uint32_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    uint32_t o = __shfl_xor(v, d, 64);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
+// Wave-aggregated append: every lane with `want` gets a unique slot in a
+// global list whose length is *counter. Returns the slot (undefined for
+// lanes without `want`).
+__device__ __forceinline__ uint32_t wave_append(uint32_t *counter, bool want) {
+  uint64_t mask = ballot64(want);
+  uint32_t total = __popcll(mask);
+  if (total == 0) return 0;
+  uint32_t lane = lane_id();
+  uint32_t leader = __ffsll((unsigned long long)mask) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(counter, total);
+  base = __shfl(base, leader, 64);
+  uint64_t below = mask & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)));
+  return base + __popcll(below);
+}
+
+// 20 s at the 100 MHz real-time counter: far beyond any legitimate wait.
+constexpr uint64_t kBarrierTimeoutTicks = 2000000000ull;
+
+// Grid-wide barrier for a persistent launch whose blocks are all resident
+// (cooperative launch). `bar` counts arrivals monotonically; a block waits
+// until every block of this generation arrived. The fences make every
+// global write before the barrier visible to every read after it across
+// XCDs. A watchdog bound turns a stuck wait into an error flag instead of a
+// hang: once `status` is non-zero every waiter leaves.
+__device__ __forceinline__ bool grid_barrier(uint64_t *bar, uint32_t nblocks, uint32_t *status) {
+  __syncthreads();
+  __shared__ uint32_t s_ok;
+  if (threadIdx.x == 0) {
+    __threadfence();
+    uint64_t arrived = atomicAdd((unsigned long long *)bar, 1ull);
+    uint64_t target = (arrived / nblocks + 1) * (uint64_t)nblocks;
+    uint32_t ok = 1;
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();   // 100 MHz clock
+    while (ld_acq64(bar) < target) {
+      if (ld_acq32(status) != 0) { ok = 0; break; }
+      if (__builtin_amdgcn_s_memrealtime() - t0 > kBarrierTimeoutTicks) {
+        atomicOr(status, ND_DERR_WATCHDOG);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __threadfence();
+    s_ok = ok;
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+
+// ---------------------------------------------------------------------------
+// Host context
+// ---------------------------------------------------------------------------
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+struct nd_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int validate = 1;
+  uint64_t mem_limit = 0;
+  uint32_t peel_blocks = 0;
+  uint32_t work_chunk = 0;
+  uint64_t watchdog = 0;
+  int cu_count = 0;
+  std::string last_error;
+
+  // graph
+  bool have_graph = false;
+  uint32_t n = 0;
+  uint64_t nnz = 0, m = 0;
+  uint32_t r = 0, s = 0;
+  bool decomposed = false;
+
+  // named device buffers (grow-only)
+  std::vector<DevBuf> bufs;
+  uint64_t bytes_held = 0;
+
+  // device views of the prepared tables (valid after a decomposition)
+  GraphView gv{};
+
+  // results
+  nd_info info{};
+  uint64_t n_r = 0;
+  uint64_t n_int = 0;
+
+  // events for phase timing
+  hipEvent_t ev[6] = {};
+  bool events_ok = false;
+};
+
+// buffer slots held by the context
+enum BufId : int {
+  B_RP = 0, B_COL, B_EID, B_EU, B_EV, B_UPLO, B_DEG,
+  B_OKEY, B_DGP, B_DGC, B_DGE,
+  B_SUP, B_UPC, B_WP, B_TRIB, B_WC, B_WT, B_TE,
+  B_CNT, B_CNT0, B_ROUND, B_UF, B_L,
+  B_F0, B_F1, B_WSCAN, B_AL0, B_AL1, B_BTOT, B_LINKQ,
+  B_SCAL, B_TMP64, B_TMP32A, B_TMP32B, B_TMP32C, B_TMP32D,
+  B_SORTK0, B_SORTK1, B_SORTV0, B_SORTV1, B_HIST,
+  B_PARENT, B_LEVEL, B_RCL,
+  B_COUNT
+};
+
+// device scalars block (one per context)
+struct DevScalars {
+  uint64_t n_s;            // s-cliques counted
+  uint64_t barrier;        // grid barrier arrivals
+  uint64_t visits, decrements, links, unites;
+  uint64_t bucket_scans;
+  uint32_t status;         // ND_DERR_* bits
+  uint32_t k;              // final level reached
+  uint32_t rounds;         // peel rounds executed
+  uint32_t fsize[2];       // frontier sizes (by round parity)
+  uint32_t kmin[2];        // bucket scan minimum (by scan parity)
+  uint32_t n_alive[2];     // alive list sizes (by scan parity)
+  uint32_t linkq_head, linkq_tail;
+  uint32_t max_outdeg;
+  uint32_t orient_round;
+  uint32_t n_kept;         // tree: kept nodes
+  uint32_t pad[5];
+};
+
+// helpers implemented in nd_api.hip
+nd_status nd_fail(nd_ctx *c, nd_status st, const std::string &msg);
+void *nd_buf(nd_ctx *c, int id, size_t bytes, nd_status *st);
+nd_status nd_hip(nd_ctx *c, hipError_t e, const char *what);
+
+// pipeline stages (each returns ND_OK or an error already recorded in ctx)
+nd_status nd_stage_prep(nd_ctx *c, GraphView *gv);
+nd_status nd_stage_count(nd_ctx *c, const GraphView &gv);
+nd_status nd_stage_peel(nd_ctx *c, const GraphView &gv);
+nd_status nd_stage_tree(nd_ctx *c, const GraphView &gv);
+nd_status nd_write_rcliques(nd_ctx *c, const GraphView &gv, uint32_t *out_dev);
+
+// small device utilities (nd_prep.hip)
+nd_status nd_exclusive_scan_u64(nd_ctx *c, const uint64_t *in_dev, uint64_t *out_dev, uint64_t n,
+                                uint64_t *total_host);
+nd_status nd_exclusive_scan_u32_to_u64(nd_ctx *c, const uint32_t *in_dev, uint64_t *out_dev,
+                                       uint64_t n, uint64_t *total_host);
+
+inline uint32_t nd_grid(uint64_t work, uint32_t block, uint32_t cap = 1u << 20) {
+  uint64_t g = (work + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (uint32_t)g;
+}

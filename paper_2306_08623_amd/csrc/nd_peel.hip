@@ -1,0 +1,607 @@
+// nd_peel.hip -- peeling rounds interleaved with hierarchy linking
+// (Algorithm 3, Section 7.1, with LINK-EFFICIENT of Algorithm 5,
+// Section 7.3), as one persistent cooperative launch.
+//
+// Round t at level k:
+//   bucket  When the frontier is empty, the remaining r-cliques are scanned
+//           for their minimum count k' (> k), and the frontier becomes every
+//           remaining r-clique with count k'. The scan also compacts the list
+//           of remaining r-cliques, so each scan only touches survivors.
+//   mark    Every frontier r-clique R gets core number k and peel round t.
+//   visit   For every frontier R and every s-clique S containing R (found by
+//           intersecting the adjacency lists of R's members), each other
+//           r-clique R' of S is classified by its peel round:
+//             - R' peeled earlier or in this round: link(R', R) -- R and R'
+//               are s-clique-adjacent and both core numbers are final;
+//             - R' still present: if no member of S was peeled before round t
+//               (S still exists) and R is the smallest-id member of S peeled
+//               in round t (so S is removed exactly once), decrement R''s
+//               count; the decrement that lowers it from k+1 to k puts R'
+//               into the next frontier (same level k).
+//   A grid barrier separates the phases. The next round starts with the
+//   collected frontier or, if it is empty, with a bucket scan.
+//
+// Work balance: every frontier r-clique contributes "probe elements" (the
+// entries of its shortest adjacency list); a per-block prefix sum over the
+// frontier lets every lane take one probe element of the global sequence.
+//
+// The link routine keeps uf (components of equal core number) and L (for a
+// component root, an r-clique of the nearest lower core it is connected to)
+// consistent with compare-and-swap; its recursive calls become a small
+// per-lane stack that spills into a global queue drained between rounds.
+#include "nd_internal.h"
+
+#include <algorithm>
+#include <cstddef>
+#include <cstring>
+
+namespace {
+
+constexpr uint32_t kPeelBlock = 256;
+constexpr uint32_t kMaxPeelBlocks = 4096;
+constexpr uint32_t kLocalStack = 8;
+constexpr uint32_t kLinkStepCap = 1u << 24;
+
+struct PeelArgs {
+  GraphView g;
+  uint64_t n_r;
+  uint32_t *cnt;      // s-clique count; the core number once peeled
+  uint32_t *round;    // peel round, ND_ALIVE while present
+  uint32_t *uf;       // union-find parent
+  uint32_t *L;        // nearest lower core link of a uf root
+  uint32_t *F0, *F1;  // frontiers by round parity
+  uint64_t *wscan;    // per frontier slot: inclusive work prefix in its segment
+  uint32_t *al0, *al1;  // remaining r-cliques by scan parity
+  uint64_t *btot;     // per block: work total of its frontier segment
+  uint32_t *linkq;    // spilled link pairs
+  uint32_t linkq_cap;
+  DevScalars *sc;
+  uint32_t nblocks;
+  uint32_t max_rounds;
+};
+
+// ---------------------------------------------------------------------------
+// union-find (lock-free: CAS link of roots by index, path halving)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t uf_find(uint32_t *uf, uint32_t x) {
+  for (;;) {
+    uint32_t p = ld_acq32(&uf[x]);
+    if (p == x) return x;
+    uint32_t gp = ld_acq32(&uf[p]);
+    if (gp == p) return p;
+    cas32(&uf[x], p, gp);
+    x = gp;
+  }
+}
+
+// Joins the sets of a and b; the smaller root id survives. True if this call
+// performed the union.
+__device__ __forceinline__ bool uf_unite(uint32_t *uf, uint32_t a, uint32_t b) {
+  for (;;) {
+    a = uf_find(uf, a);
+    b = uf_find(uf, b);
+    if (a == b) return false;
+    if (a > b) { uint32_t t = a; a = b; b = t; }
+    if (cas32(&uf[b], b, a)) return true;
+  }
+}
+
+struct LinkCtx {
+  uint32_t *uf;
+  uint32_t *L;
+  const uint32_t *nd;
+  uint32_t *linkq;
+  uint32_t linkq_cap;
+  DevScalars *sc;
+  uint64_t links, unites;
+};
+
+// The spill queue is a ring of linkq_cap (a power of two) pairs addressed by
+// monotone head/tail counters; head only moves between grid barriers.
+__device__ __forceinline__ void spill(LinkCtx &c, uint32_t R, uint32_t Q) {
+  const uint32_t i = atomicAdd(&c.sc->linkq_tail, 1u);
+  const uint32_t h = ld_acq32(&c.sc->linkq_head);
+  if (i - h < c.linkq_cap) {
+    const uint64_t slot = i & (c.linkq_cap - 1);
+    c.linkq[2 * slot] = R;
+    c.linkq[2 * slot + 1] = Q;
+  } else {
+    atomicOr(&c.sc->status, ND_DERR_LINKQ);
+  }
+}
+
+__device__ __forceinline__ uint64_t min64(uint64_t a, uint64_t b) { return a < b ? a : b; }
+
+// LINK-EFFICIENT (Algorithm 5) for the pair (R0, Q0), whose core numbers are
+// both final. Recursive calls are pushed on a small stack; pairs that do not
+// fit go to the global queue.
+__device__ void link_efficient(LinkCtx &c, uint32_t R0, uint32_t Q0) {
+  uint32_t stR[kLocalStack], stQ[kLocalStack];
+  uint32_t sp = 0;
+  stR[sp] = R0;
+  stQ[sp] = Q0;
+  sp++;
+  uint32_t steps = 0;
+  while (sp > 0) {
+    sp--;
+    uint32_t R = stR[sp], Q = stQ[sp];
+    if (R == ND_NONE || Q == ND_NONE) continue;
+    if (++steps > kLinkStepCap) {
+      atomicOr(&c.sc->status, ND_DERR_WATCHDOG);
+      return;
+    }
+    c.links++;
+    auto push = [&](uint32_t a, uint32_t b) {
+      if (a == ND_NONE || b == ND_NONE) return;
+      if (sp < kLocalStack) {
+        stR[sp] = a;
+        stQ[sp] = b;
+        sp++;
+      } else {
+        spill(c, a, b);
+      }
+    };
+    if (c.nd[Q] < c.nd[R]) { uint32_t t = R; R = Q; Q = t; }
+    R = uf_find(c.uf, R);
+    Q = uf_find(c.uf, Q);
+    const uint32_t ndR = c.nd[R];
+    if (ndR == c.nd[Q]) {
+      if (R == Q) continue;
+      if (uf_unite(c.uf, R, Q)) c.unites++;
+      // the root that lost its role hands its nearest-lower-core link to the
+      // surviving root
+      uint32_t pR = uf_find(c.uf, R);
+      if (pR != R) push(ld_acq32(&c.L[R]), pR);
+      uint32_t pQ = uf_find(c.uf, Q);
+      if (pQ != Q) push(ld_acq32(&c.L[Q]), pQ);
+    } else {
+      // ND[R] < ND[Q]: R may become Q's nearest lower core, and R must be
+      // connected with Q's current nearest lower core
+      uint32_t spins = 0;
+      for (;;) {
+        if (++spins > kLinkStepCap) {
+          atomicOr(&c.sc->status, ND_DERR_WATCHDOG);
+          return;
+        }
+        const uint32_t LQ = ld_acq32(&c.L[Q]);
+        Q = uf_find(c.uf, Q);
+        if (cas32(&c.L[Q], ND_NONE, R)) {
+          uint32_t pQ = uf_find(c.uf, Q);
+          if (pQ != Q) push(R, pQ);   // Q was merged meanwhile
+          break;
+        }
+        if (LQ == ND_NONE) continue;  // L[Q] was set concurrently: read again
+        if (c.nd[LQ] < ndR) {
+          if (cas32(&c.L[Q], LQ, R)) {
+            uint32_t pQ = uf_find(c.uf, Q);
+            if (pQ != Q) push(R, pQ);
+            push(R, LQ);
+            break;
+          }
+        } else {
+          push(R, LQ);
+          break;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-(r,s) s-clique discovery around a frontier r-clique
+// ---------------------------------------------------------------------------
+
+template <int R_, int S_>
+struct Shape;
+
+// (1,2): R = vertex v; every neighbour x closes an s-clique {v, x}.
+template <>
+struct Shape<1, 2> {
+  static constexpr int kOthers = 1;
+  __device__ static uint32_t work(const GraphView &g, uint32_t R) {
+    return (uint32_t)(g.rp[R + 1] - g.rp[R]);
+  }
+  __device__ static bool visit(const GraphView &g, uint32_t R, uint32_t i, uint32_t *o) {
+    o[0] = g.col[g.rp[R] + i];
+    return true;
+  }
+};
+
+// (2,3): R = edge {u, v}; probe the shorter row, search the longer; the two
+// slots give the ids of edges {u, x} and {v, x}.
+template <>
+struct Shape<2, 3> {
+  static constexpr int kOthers = 2;
+  __device__ static uint32_t work(const GraphView &g, uint32_t R) {
+    const uint32_t u = g.eu[R], v = g.ev[R];
+    const uint64_t du = g.rp[u + 1] - g.rp[u], dv = g.rp[v + 1] - g.rp[v];
+    return (uint32_t)(du < dv ? du : dv);
+  }
+  __device__ static bool visit(const GraphView &g, uint32_t R, uint32_t i, uint32_t *o) {
+    uint32_t p = g.eu[R], q = g.ev[R];
+    if (g.rp[q + 1] - g.rp[q] < g.rp[p + 1] - g.rp[p]) { uint32_t t = p; p = q; q = t; }
+    const uint64_t sp = g.rp[p] + i;
+    const uint32_t x = g.col[sp];
+    const uint64_t bq = g.rp[q], eq = g.rp[q + 1];
+    const uint64_t sq = find_u32<uint64_t>(g.col, bq, eq, x);
+    if (sq == eq) return false;
+    o[0] = g.eid[sp];
+    o[1] = g.eid[sq];
+    return true;
+  }
+};
+
+// (3,4): R = triangle with edges e0, e1, e2; the common neighbours of its
+// vertices are the entries common to W(e0), W(e1), W(e2); the positions give
+// the ids of the three other triangles.
+template <>
+struct Shape<3, 4> {
+  static constexpr int kOthers = 3;
+  __device__ static uint32_t work(const GraphView &g, uint32_t R) {
+    const uint32_t e0 = g.te[3ull * R], e1 = g.te[3ull * R + 1], e2 = g.te[3ull * R + 2];
+    uint64_t s0 = g.wp[e0 + 1] - g.wp[e0], s1 = g.wp[e1 + 1] - g.wp[e1],
+             s2 = g.wp[e2 + 1] - g.wp[e2];
+    uint64_t mn = s0 < s1 ? s0 : s1;
+    mn = mn < s2 ? mn : s2;
+    return (uint32_t)mn;
+  }
+  __device__ static bool visit(const GraphView &g, uint32_t R, uint32_t i, uint32_t *o) {
+    uint32_t e0 = g.te[3ull * R], e1 = g.te[3ull * R + 1], e2 = g.te[3ull * R + 2];
+    uint64_t s0 = g.wp[e0 + 1] - g.wp[e0], s1 = g.wp[e1 + 1] - g.wp[e1],
+             s2 = g.wp[e2 + 1] - g.wp[e2];
+    // probe the shortest list: rotate it into e0
+    if (s1 < s0 && s1 <= s2) {
+      uint32_t t = e0; e0 = e1; e1 = t;
+    } else if (s2 < s0 && s2 < s1) {
+      uint32_t t = e0; e0 = e2; e2 = t;
+    }
+    const uint64_t p0 = g.wp[e0] + i;
+    const uint32_t x = g.wc[p0];
+    const uint64_t b1 = g.wp[e1], f1 = g.wp[e1 + 1];
+    const uint64_t p1 = find_u32<uint64_t>(g.wc, b1, f1, x);
+    if (p1 == f1) return false;
+    const uint64_t b2 = g.wp[e2], f2 = g.wp[e2 + 1];
+    const uint64_t p2 = find_u32<uint64_t>(g.wc, b2, f2, x);
+    if (p2 == f2) return false;
+    o[0] = g.wt[p0];
+    o[1] = g.wt[p1];
+    o[2] = g.wt[p2];
+    return true;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// the persistent kernel
+// ---------------------------------------------------------------------------
+
+template <int R_, int S_>
+__global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
+  using Sh = Shape<R_, S_>;
+  constexpr int NO = Sh::kOthers;
+  __shared__ uint64_t s_boff[kMaxPeelBlocks + 1];
+  __shared__ uint32_t s_red[kPeelBlock / 64];
+  __shared__ uint64_t s_red64[kPeelBlock / 64];
+
+  DevScalars *sc = a.sc;
+  const GraphView &g = a.g;
+  const uint32_t nb = a.nblocks;
+  const uint32_t lane = lane_id();
+  const uint32_t wv = threadIdx.x / 64;
+  const uint64_t gtid = blockIdx.x * (uint64_t)kPeelBlock + threadIdx.x;
+  const uint64_t nthreads = (uint64_t)nb * kPeelBlock;
+
+  LinkCtx lc;
+  lc.uf = a.uf;
+  lc.L = a.L;
+  lc.nd = a.cnt;
+  lc.linkq = a.linkq;
+  lc.linkq_cap = a.linkq_cap;
+  lc.sc = sc;
+  lc.links = 0;
+  lc.unites = 0;
+  uint64_t visits = 0, decs = 0, scans = 0;
+
+  uint32_t k = 0;
+  uint32_t t = 0;
+  uint32_t q = 0;   // bucket scans done
+  bool done = false;
+
+  while (!done) {
+    if (t >= a.max_rounds) {
+      if (gtid == 0) atomicOr(&sc->status, ND_DERR_WATCHDOG);
+      break;
+    }
+    uint32_t *F = (t & 1) ? a.F1 : a.F0;
+    uint32_t *Fn = (t & 1) ? a.F0 : a.F1;
+    uint32_t f = ld_acq32(&sc->fsize[t & 1]);
+
+    if (f == 0) {
+      // ---- bucket scan: new level = minimum count of the remaining r-cliques
+      const uint32_t qp = q & 1;
+      const uint32_t *in = qp ? a.al1 : a.al0;
+      uint32_t *out = qp ? a.al0 : a.al1;
+      const uint64_t nin = (q == 0) ? a.n_r : ld_acq32(&sc->n_alive[qp]);
+      uint32_t mn = ND_NONE;
+      for (uint64_t base = blockIdx.x * (uint64_t)kPeelBlock; base < nin; base += nthreads) {
+        const uint64_t i = base + threadIdx.x;
+        bool keep = false;
+        uint32_t id = 0;
+        if (i < nin) {
+          id = (q == 0) ? (uint32_t)i : in[i];
+          if (a.round[id] == ND_ALIVE) {
+            keep = true;
+            uint32_t cv = a.cnt[id];
+            mn = cv < mn ? cv : mn;
+          }
+        }
+        uint32_t slot = wave_append(&sc->n_alive[qp ^ 1], keep);
+        if (keep) out[slot] = id;
+      }
+      mn = wave_min32(mn);
+      if (lane == 0) s_red[wv] = mn;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        uint32_t bm = ND_NONE;
+        for (uint32_t w = 0; w < kPeelBlock / 64; w++) bm = s_red[w] < bm ? s_red[w] : bm;
+        if (bm != ND_NONE) atomicMin(&sc->kmin[qp], bm);
+      }
+      if (!grid_barrier(&sc->barrier, nb, &sc->status)) break;
+      const uint32_t nout = ld_acq32(&sc->n_alive[qp ^ 1]);
+      if (nout == 0) {
+        done = true;
+        break;
+      }
+      const uint32_t kq = ld_acq32(&sc->kmin[qp]);
+      if (gtid == 0) {
+        sc->n_alive[qp] = 0;         // becomes the output counter of the next scan
+        sc->kmin[qp ^ 1] = ND_NONE;  // minimum of the next scan
+      }
+      for (uint64_t base = blockIdx.x * (uint64_t)kPeelBlock; base < nout; base += nthreads) {
+        const uint64_t i = base + threadIdx.x;
+        bool take = false;
+        uint32_t id = 0;
+        if (i < nout) {
+          id = out[i];
+          take = a.cnt[id] == kq;
+        }
+        uint32_t slot = wave_append(&sc->fsize[t & 1], take);
+        if (take) F[slot] = id;
+      }
+      scans++;
+      q++;
+      k = kq;
+      if (!grid_barrier(&sc->barrier, nb, &sc->status)) break;
+      f = ld_acq32(&sc->fsize[t & 1]);
+    }
+
+    // ---- mark: core number and peel round; per-segment work prefix sums
+    const uint64_t seg = (f + nb - 1) / nb;
+    const uint64_t sbeg = min64((uint64_t)blockIdx.x * seg, f);
+    const uint64_t send = min64(sbeg + seg, f);
+    uint64_t run = 0;
+    for (uint64_t base = sbeg; base < send; base += kPeelBlock) {
+      const uint64_t i = base + threadIdx.x;
+      uint32_t w = 0;
+      if (i < send) {
+        const uint32_t R = F[i];
+        a.round[R] = t;
+        a.cnt[R] = k;
+        w = Sh::work(g, R);
+      }
+      // block-wide inclusive scan of w
+      uint32_t incl = wave_incl_scan(w);
+      if (lane == 63) s_red64[wv] = incl;
+      __syncthreads();
+      uint64_t wpre = 0, btot = 0;
+      for (uint32_t x = 0; x < kPeelBlock / 64; x++) {
+        if (x < wv) wpre += s_red64[x];
+        btot += s_red64[x];
+      }
+      if (i < send) a.wscan[i] = run + wpre + incl;
+      run += btot;
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) a.btot[blockIdx.x] = run;
+    if (gtid == 0) sc->fsize[(t + 1) & 1] = 0;
+    if (!grid_barrier(&sc->barrier, nb, &sc->status)) break;
+
+    // ---- visit: one probe element per lane over the whole frontier
+    {
+      // exclusive scan of the block totals into LDS (each thread owns a run)
+      const uint32_t per = (nb + kPeelBlock - 1) / kPeelBlock;
+      const uint32_t j0 = threadIdx.x * per;
+      uint64_t mine = 0;
+      for (uint32_t j = j0; j < j0 + per && j < nb; j++) mine += a.btot[j];
+      uint64_t incl = mine;
+      for (int d = 1; d < 64; d <<= 1) {
+        uint64_t y = __shfl_up(incl, d, 64);
+        if (lane >= (uint32_t)d) incl += y;
+      }
+      if (lane == 63) s_red64[wv] = incl;
+      __syncthreads();
+      uint64_t acc = incl - mine;
+      for (uint32_t x = 0; x < wv; x++) acc += s_red64[x];
+      for (uint32_t j = j0; j < j0 + per && j < nb; j++) {
+        s_boff[j] = acc;
+        acc += a.btot[j];
+      }
+      if (threadIdx.x == kPeelBlock - 1) s_boff[nb] = acc;
+      __syncthreads();
+    }
+    const uint64_t P = s_boff[nb];
+    for (uint64_t base = blockIdx.x * (uint64_t)kPeelBlock + wv * 64ull; base < P;
+         base += nthreads) {
+      const uint64_t p = base + lane;
+      uint32_t others[NO];
+      bool push[NO];
+#pragma unroll
+      for (int j = 0; j < NO; j++) push[j] = false;
+      if (p < P) {
+        // block segment holding p, then the frontier slot inside it
+        uint32_t lo = 0, hi = nb;   // s_boff[lo] <= p < s_boff[hi]
+        while (hi - lo > 1) {
+          uint32_t mid = (lo + hi) >> 1;
+          if (s_boff[mid] <= p) lo = mid;
+          else hi = mid;
+        }
+        const uint64_t qoff = p - s_boff[lo];
+        const uint64_t b0 = min64((uint64_t)lo * seg, f);
+        const uint64_t b1 = min64(b0 + seg, f);
+        uint64_t x0 = b0, x1 = b1;   // first slot with wscan > qoff
+        while (x0 < x1) {
+          uint64_t mid = (x0 + x1) >> 1;
+          if (a.wscan[mid] <= qoff) x0 = mid + 1;
+          else x1 = mid;
+        }
+        const uint32_t R = F[x0];
+        const uint64_t before = (x0 > b0) ? a.wscan[x0 - 1] : 0;
+        const uint32_t idx = (uint32_t)(qoff - before);
+        if (Sh::visit(g, R, idx, others)) {
+          visits++;
+          uint32_t rr[NO];
+          bool dead = false, lead = true;
+#pragma unroll
+          for (int j = 0; j < NO; j++) {
+            rr[j] = a.round[others[j]];
+            dead |= rr[j] < t;
+            lead &= !(rr[j] == t && others[j] < R);
+          }
+          if (!dead && lead) {
+#pragma unroll
+            for (int j = 0; j < NO; j++) {
+              if (rr[j] == ND_ALIVE) {
+                uint32_t old = atomicSub(&a.cnt[others[j]], 1u);
+                decs++;
+                push[j] = (old == k + 1);
+              }
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < NO; j++) {
+            if (rr[j] < t || (rr[j] == t && R < others[j])) link_efficient(lc, others[j], R);
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NO; j++) {
+        uint32_t slot = wave_append(&sc->fsize[(t + 1) & 1], push[j]);
+        if (push[j]) Fn[slot] = others[j];
+      }
+    }
+    if (!grid_barrier(&sc->barrier, nb, &sc->status)) break;
+
+    // ---- drain spilled link pairs (rare): repeat until the queue is empty
+    bool ok = true;
+    for (;;) {
+      const uint32_t h = ld_acq32(&sc->linkq_head);
+      const uint32_t tl = ld_acq32(&sc->linkq_tail);
+      if (h == tl) break;
+      if (tl - h > a.linkq_cap) {   // overflowed: the status bit is already set
+        ok = false;
+        break;
+      }
+      for (uint64_t d = gtid; d < (uint32_t)(tl - h); d += nthreads) {
+        const uint64_t slot = (h + (uint32_t)d) & (a.linkq_cap - 1);
+        link_efficient(lc, a.linkq[2 * slot], a.linkq[2 * slot + 1]);
+      }
+      if (!grid_barrier(&sc->barrier, nb, &sc->status)) { ok = false; break; }
+      if (gtid == 0) sc->linkq_head = tl;
+      if (!grid_barrier(&sc->barrier, nb, &sc->status)) { ok = false; break; }
+    }
+    if (!ok) break;
+    t++;
+  }
+
+  // statistics
+  uint64_t v = wave_sum64(visits), d = wave_sum64(decs), l = wave_sum64(lc.links),
+           u = wave_sum64(lc.unites);
+  if (lane == 0) {
+    if (v) atomicAdd((unsigned long long *)&sc->visits, (unsigned long long)v);
+    if (d) atomicAdd((unsigned long long *)&sc->decrements, (unsigned long long)d);
+    if (l) atomicAdd((unsigned long long *)&sc->links, (unsigned long long)l);
+    if (u) atomicAdd((unsigned long long *)&sc->unites, (unsigned long long)u);
+  }
+  if (gtid == 0) {
+    sc->rounds = t;
+    sc->k = k;
+    sc->bucket_scans = scans;
+  }
+}
+
+__global__ void k_iota(uint32_t *a, uint64_t n) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    a[i] = (uint32_t)i;
+}
+
+template <int R_, int S_>
+nd_status launch_peel(nd_ctx *c, PeelArgs &pa) {
+  const void *kern = (const void *)k_peel<R_, S_>;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kPeelBlock, 0) != hipSuccess ||
+      per_cu < 1)
+    return nd_fail(c, ND_E_DEVICE, "occupancy query failed for the peel kernel");
+  uint64_t cap = (uint64_t)per_cu * (uint64_t)c->cu_count;
+  cap = std::min<uint64_t>(cap, kMaxPeelBlocks);
+  uint64_t want = c->peel_blocks ? c->peel_blocks : cap;
+  uint32_t nb = (uint32_t)std::max<uint64_t>(1, std::min(want, cap));
+  pa.nblocks = nb;
+  void *args[] = {&pa};
+  return nd_hip(c, hipLaunchCooperativeKernel(kern, dim3(nb), dim3(kPeelBlock), args, 0,
+                                              c->stream),
+                "peel launch");
+}
+
+}  // namespace
+
+nd_status nd_stage_peel(nd_ctx *c, const GraphView &g) {
+  nd_status st;
+  const uint64_t nr = c->n_r;
+  DevScalars *sc = (DevScalars *)c->bufs[B_SCAL].p;
+  if (nr == 0) return ND_OK;
+  if (nr >= 0xFFFFFFFFull) return nd_fail(c, ND_E_OVERFLOW, "r-clique ids exceed 32 bits");
+  PeelArgs pa;
+  pa.g = g;
+  pa.n_r = nr;
+  pa.cnt = (uint32_t *)c->bufs[B_CNT].p;
+  if (!(pa.round = (uint32_t *)nd_buf(c, B_ROUND, nr * 4, &st))) return st;
+  if (!(pa.uf = (uint32_t *)nd_buf(c, B_UF, nr * 4, &st))) return st;
+  if (!(pa.L = (uint32_t *)nd_buf(c, B_L, nr * 4, &st))) return st;
+  if (!(pa.F0 = (uint32_t *)nd_buf(c, B_F0, nr * 4, &st))) return st;
+  if (!(pa.F1 = (uint32_t *)nd_buf(c, B_F1, nr * 4, &st))) return st;
+  if (!(pa.wscan = (uint64_t *)nd_buf(c, B_WSCAN, nr * 8, &st))) return st;
+  if (!(pa.al0 = (uint32_t *)nd_buf(c, B_AL0, nr * 4, &st))) return st;
+  if (!(pa.al1 = (uint32_t *)nd_buf(c, B_AL1, nr * 4, &st))) return st;
+  if (!(pa.btot = (uint64_t *)nd_buf(c, B_BTOT, (kMaxPeelBlocks + 1) * 8, &st))) return st;
+  pa.linkq_cap = 1u << 16;
+  while (pa.linkq_cap < nr && pa.linkq_cap < (1u << 26)) pa.linkq_cap <<= 1;
+  if (!(pa.linkq = (uint32_t *)nd_buf(c, B_LINKQ, pa.linkq_cap * 8ull, &st))) return st;
+  pa.sc = sc;
+  uint64_t wd = c->watchdog ? c->watchdog : nr + 2;
+  pa.max_rounds = (uint32_t)std::min<uint64_t>(wd, 0xFFFFFFF0ull);
+
+  if ((st = nd_hip(c, hipMemsetAsync(pa.round, 0xFF, nr * 4, c->stream), "round")) != ND_OK)
+    return st;
+  if ((st = nd_hip(c, hipMemsetAsync(pa.L, 0xFF, nr * 4, c->stream), "L")) != ND_OK) return st;
+  hipLaunchKernelGGL(k_iota, dim3(nd_grid(nr, 256, 16384)), dim3(256), 0, c->stream, pa.uf, nr);
+  // scalars: counters zero, kmin = NONE, barrier zero
+  DevScalars init;
+  memset(&init, 0, sizeof(init));
+  init.kmin[0] = init.kmin[1] = ND_NONE;
+  // keep n_s and max_outdeg: copy only the fields the peel owns
+  const size_t off_lo = offsetof(DevScalars, barrier);
+  const size_t off_hi = offsetof(DevScalars, max_outdeg);
+  if ((st = nd_hip(c,
+                   hipMemcpyAsync((char *)sc + off_lo, (char *)&init + off_lo, off_hi - off_lo,
+                                  hipMemcpyHostToDevice, c->stream),
+                   "peel scalars")) != ND_OK)
+    return st;
+  if ((st = nd_hip(c, hipStreamSynchronize(c->stream), "peel scalars sync")) != ND_OK) return st;
+
+  const uint32_t r = c->r, s = c->s;
+  if (r == 1 && s == 2) return launch_peel<1, 2>(c, pa);
+  if (r == 2 && s == 3) return launch_peel<2, 3>(c, pa);
+  if (r == 3 && s == 4) return launch_peel<3, 4>(c, pa);
+  return nd_fail(c, ND_E_UNSUPPORTED, "peeling for this (r,s) is not built");
+}

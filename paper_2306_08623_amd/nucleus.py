@@ -1,0 +1,299 @@
+"""Python binding of the gfx950 nucleus decomposition library (``libnucleus.so``).
+
+Argument marshalling only: every step of the decomposition runs in the HIP
+kernels of the library. The names mirror the C ABI in ``include/nucleus.h``.
+PyTorch is used, when present, only to hand device memory (CUDA tensors) and
+the current HIP stream to the library.
+
+The library must have been built (``python -m paper_2306_08623_amd.build`` or
+``__graft_entry__.build()``); importing a context without it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnucleus.so")
+
+ND_OK = 0
+ND_E_INVALID_ARG = 1
+ND_E_BAD_GRAPH = 2
+ND_E_UNSUPPORTED = 3
+ND_E_OOM = 4
+ND_E_OVERFLOW = 5
+ND_E_DEVICE = 6
+ND_E_WATCHDOG = 7
+ND_E_STATE = 8
+ND_E_CANCELLED = 9
+
+ND_MEM_HOST = 0
+ND_MEM_DEVICE = 1
+
+NONE64 = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+# Every function the C ABI exports (kept in sync with include/nucleus.h).
+EXPORTS = [
+    "nd_create", "nd_destroy", "nd_load_csr", "nd_set_rs", "nd_decompose", "nd_sync",
+    "nd_get_info", "nd_get_rcliques", "nd_get_counts", "nd_get_coreness", "nd_get_tree",
+    "nd_status_str", "nd_last_error",
+]
+
+
+class Options(C.Structure):
+    _fields_ = [
+        ("device", C.c_int),
+        ("hip_stream", C.c_void_p),
+        ("validate", C.c_int),
+        ("mem_limit", C.c_uint64),
+        ("peel_blocks", C.c_uint32),
+        ("work_chunk", C.c_uint32),
+        ("watchdog", C.c_uint64),
+    ]
+
+
+class Info(C.Structure):
+    _fields_ = [
+        ("n", C.c_uint32), ("r", C.c_uint32), ("s", C.c_uint32),
+        ("m", C.c_uint64),
+        ("n_r", C.c_uint64),
+        ("n_s", C.c_uint64),
+        ("k", C.c_uint32),
+        ("rounds", C.c_uint32),
+        ("n_int", C.c_uint64),
+        ("visits", C.c_uint64),
+        ("decrements", C.c_uint64),
+        ("links", C.c_uint64),
+        ("unites", C.c_uint64),
+        ("bucket_scans", C.c_uint64),
+        ("max_outdeg", C.c_uint32),
+        ("orient_rounds", C.c_uint32),
+        ("ms_prep", C.c_float),
+        ("ms_count", C.c_float),
+        ("ms_peel", C.c_float),
+        ("ms_tree", C.c_float),
+        ("device_bytes", C.c_uint64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class NucleusError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"nucleus error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load ``libnucleus.so``; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: build the HIP library first "
+            "(python -m paper_2306_08623_amd.build)")
+    lib = C.CDLL(path)
+    vp = C.c_void_p
+    u64p = C.POINTER(C.c_uint64)
+    u32p = C.POINTER(C.c_uint32)
+    lib.nd_create.argtypes = [C.POINTER(vp), C.POINTER(Options)]
+    lib.nd_create.restype = C.c_int
+    lib.nd_destroy.argtypes = [vp]
+    lib.nd_destroy.restype = None
+    lib.nd_load_csr.argtypes = [vp, C.c_uint32, C.c_uint64, vp, vp, C.c_int]
+    lib.nd_load_csr.restype = C.c_int
+    lib.nd_set_rs.argtypes = [vp, C.c_uint32, C.c_uint32]
+    lib.nd_set_rs.restype = C.c_int
+    lib.nd_decompose.argtypes = [vp]
+    lib.nd_decompose.restype = C.c_int
+    lib.nd_sync.argtypes = [vp]
+    lib.nd_sync.restype = C.c_int
+    lib.nd_get_info.argtypes = [vp, C.POINTER(Info)]
+    lib.nd_get_info.restype = C.c_int
+    for name in ("nd_get_rcliques", "nd_get_counts", "nd_get_coreness"):
+        getattr(lib, name).argtypes = [vp, vp, C.c_int]
+        getattr(lib, name).restype = C.c_int
+    lib.nd_get_tree.argtypes = [vp, vp, vp, C.c_int]
+    lib.nd_get_tree.restype = C.c_int
+    lib.nd_status_str.argtypes = [C.c_int]
+    lib.nd_status_str.restype = C.c_char_p
+    lib.nd_last_error.argtypes = [vp]
+    lib.nd_last_error.restype = C.c_char_p
+    del u64p, u32p
+    _lib = lib
+    return lib
+
+
+def _ptr(a) -> tuple[int, int]:
+    """(address, memory kind) of a numpy array or a torch tensor."""
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data, ND_MEM_HOST
+    if hasattr(a, "data_ptr") and hasattr(a, "is_cuda"):
+        return a.data_ptr(), (ND_MEM_DEVICE if a.is_cuda else ND_MEM_HOST)
+    raise TypeError(f"unsupported array type {type(a)}")
+
+
+def _current_stream(device: int):
+    try:
+        import torch
+    except ImportError:  # pragma: no cover - torch is part of the image
+        return None
+    if not torch.cuda.is_available():
+        return None
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+@dataclass
+class Result:
+    r: int
+    s: int
+    info: dict
+    rcliques: np.ndarray   # uint32 [n_r, r]
+    counts: np.ndarray     # uint32 [n_r]
+    coreness: np.ndarray   # uint32 [n_r]
+    parent: np.ndarray     # uint64 [n_r + n_int]
+    level: np.ndarray      # uint32 [n_int]
+
+
+class Context:
+    """One library context (device buffers, stream, last result)."""
+
+    def __init__(self, device: int = 0, stream=None, validate: bool = True, mem_limit: int = 0,
+                 peel_blocks: int = 0, work_chunk: int = 0, watchdog: int = 0,
+                 use_torch_stream: bool = True):
+        self.lib = load_library()
+        opt = Options()
+        opt.device = device
+        if stream is None and use_torch_stream:
+            stream = _current_stream(device)
+        opt.hip_stream = stream if stream is None or isinstance(stream, C.c_void_p) else C.c_void_p(stream)
+        opt.validate = 1 if validate else 0
+        opt.mem_limit = mem_limit
+        opt.peel_blocks = peel_blocks
+        opt.work_chunk = work_chunk
+        opt.watchdog = watchdog
+        h = C.c_void_p()
+        st = self.lib.nd_create(C.byref(h), C.byref(opt))
+        if st != ND_OK:
+            raise NucleusError(st, self.lib.nd_status_str(st).decode())
+        self.h = h
+        self.r = self.s = 0
+
+    # -- error handling ----------------------------------------------------
+    def _check(self, st: int):
+        if st != ND_OK:
+            msg = self.lib.nd_last_error(self.h).decode() or self.lib.nd_status_str(st).decode()
+            raise NucleusError(st, msg)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.nd_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- C ABI mirrors -----------------------------------------------------
+    def nd_load_csr(self, n: int, row_ptr, col):
+        rp_ptr, kind = _ptr(row_ptr)
+        col_ptr, kind2 = _ptr(col)
+        if kind != kind2:
+            raise ValueError("row_ptr and col must live in the same memory")
+        nnz = int(row_ptr[-1]) if kind == ND_MEM_HOST else int(col.numel())
+        self._keep = (row_ptr, col)
+        self._check(self.lib.nd_load_csr(self.h, n, nnz, rp_ptr, col_ptr, kind))
+
+    def load_csr(self, csr):
+        rp = np.ascontiguousarray(csr.row_ptr, dtype=np.uint64)
+        col = np.ascontiguousarray(csr.col, dtype=np.uint32)
+        if col.size == 0:
+            col = np.zeros(1, dtype=np.uint32)
+            self._keep = (rp, col)
+            self._check(self.lib.nd_load_csr(self.h, csr.n, 0, rp.ctypes.data, col.ctypes.data,
+                                             ND_MEM_HOST))
+            return
+        self._keep = (rp, col)
+        self._check(self.lib.nd_load_csr(self.h, csr.n, int(rp[-1]), rp.ctypes.data,
+                                         col.ctypes.data, ND_MEM_HOST))
+
+    def nd_set_rs(self, r: int, s: int):
+        self._check(self.lib.nd_set_rs(self.h, r, s))
+        self.r, self.s = r, s
+
+    def nd_decompose(self):
+        self._check(self.lib.nd_decompose(self.h))
+
+    def nd_sync(self):
+        self._check(self.lib.nd_sync(self.h))
+
+    def nd_get_info(self) -> dict:
+        info = Info()
+        self._check(self.lib.nd_get_info(self.h, C.byref(info)))
+        return info.as_dict()
+
+    def nd_get_rcliques(self) -> np.ndarray:
+        info = self.nd_get_info()
+        out = np.zeros((info["n_r"], info["r"]), dtype=np.uint32)
+        self._check(self.lib.nd_get_rcliques(self.h, out.ctypes.data if out.size else None,
+                                             ND_MEM_HOST))
+        return out
+
+    def nd_get_counts(self) -> np.ndarray:
+        n_r = self.nd_get_info()["n_r"]
+        out = np.zeros(n_r, dtype=np.uint32)
+        self._check(self.lib.nd_get_counts(self.h, out.ctypes.data if out.size else None,
+                                           ND_MEM_HOST))
+        return out
+
+    def nd_get_coreness(self, out=None):
+        n_r = self.nd_get_info()["n_r"]
+        if out is None:
+            out = np.zeros(n_r, dtype=np.uint32)
+        p, kind = _ptr(out)
+        self._check(self.lib.nd_get_coreness(self.h, p if n_r else None, kind))
+        return out
+
+    def nd_get_tree(self) -> tuple[np.ndarray, np.ndarray]:
+        info = self.nd_get_info()
+        n_r, n_int = info["n_r"], info["n_int"]
+        parent = np.zeros(n_r + n_int, dtype=np.uint64)
+        level = np.zeros(n_int, dtype=np.uint32)
+        self._check(self.lib.nd_get_tree(self.h, parent.ctypes.data if parent.size else None,
+                                         level.ctypes.data if level.size else None, ND_MEM_HOST))
+        return parent, level
+
+    # -- convenience --------------------------------------------------------
+    def decompose(self, csr, r: int, s: int) -> Result:
+        self.load_csr(csr)
+        self.nd_set_rs(r, s)
+        self.nd_decompose()
+        return self.result()
+
+    def result(self) -> Result:
+        info = self.nd_get_info()
+        parent, level = self.nd_get_tree()
+        return Result(r=info["r"], s=info["s"], info=info, rcliques=self.nd_get_rcliques(),
+                      counts=self.nd_get_counts(), coreness=self.nd_get_coreness(),
+                      parent=parent, level=level)
+
+
+def decompose(csr, r: int, s: int, device: int = 0, **opts) -> Result:
+    with Context(device=device, **opts) as ctx:
+        return ctx.decompose(csr, r, s)
