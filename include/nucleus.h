@@ -145,7 +145,8 @@ nd_status nd_get_tree(nd_ctx *ctx, uint64_t *parent, uint32_t *level, nd_mem whe
 
 const char *nd_status_str(nd_status st);
 
-/* Message of the last error of this context (empty string if none). */
+/* Message of the last error of this context (empty string if none). With
+ * ctx == NULL: the message of the last failed nd_create on this thread. */
 const char *nd_last_error(const nd_ctx *ctx);
 
 #ifdef __cplusplus

@@ -36,13 +36,36 @@ def _compile(src: str) -> str:
     return obj
 
 
+def _runtime_dirs() -> list[str]:
+    """Directories to search for the HIP runtime at load time.
+
+    PyTorch ships its own libamdhip64.so.7 (same SONAME as /opt/rocm's). A
+    process holds only one library per SONAME, so the library must run on
+    the one torch loads; it is searched first, /opt/rocm/lib second.
+    """
+    dirs = []
+    try:
+        import importlib.util
+        spec = importlib.util.find_spec("torch")
+        if spec and spec.origin:
+            tdir = os.path.join(os.path.dirname(spec.origin), "lib")
+            if os.path.exists(os.path.join(tdir, "libamdhip64.so")):
+                dirs.append(tdir)
+    except Exception:
+        pass
+    dirs.append("/opt/rocm/lib")
+    return dirs
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    rpath = ":".join(_runtime_dirs())
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs,
+           f"-Wl,-rpath,{rpath}", "-Wl,--disable-new-dtags", "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)

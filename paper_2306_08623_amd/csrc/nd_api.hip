@@ -84,7 +84,18 @@ const char *nd_status_str(nd_status st) {
   return "unknown status";
 }
 
-const char *nd_last_error(const nd_ctx *c) { return c ? c->last_error.c_str() : ""; }
+// message of the last failed nd_create on this thread (no context exists)
+static thread_local std::string g_create_error;
+
+const char *nd_last_error(const nd_ctx *c) {
+  return c ? c->last_error.c_str() : g_create_error.c_str();
+}
+
+static nd_status create_fail(nd_ctx *c, nd_status st, const std::string &msg) {
+  g_create_error = msg;
+  delete c;
+  return st;
+}
 
 nd_status nd_create(nd_ctx **out, const nd_options *opt) {
   if (!out) return ND_E_INVALID_ARG;
@@ -100,32 +111,29 @@ nd_status nd_create(nd_ctx **out, const nd_options *opt) {
     c->work_chunk = opt->work_chunk;
     c->watchdog = opt->watchdog;
   }
+  g_create_error.clear();
   int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev <= 0) {
     (void)hipGetLastError();
-    delete c;
-    return ND_E_DEVICE;
+    return create_fail(c, ND_E_DEVICE,
+                       std::string("hipGetDeviceCount: ") + hipGetErrorString(e) +
+                           " (devices: " + std::to_string(ndev) + ")");
   }
-  if (c->device < 0 || c->device >= ndev) {
-    delete c;
-    return ND_E_INVALID_ARG;
-  }
-  if (set_dev(c) != ND_OK) {
-    delete c;
-    return ND_E_DEVICE;
-  }
-  if (hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount, c->device) !=
-          hipSuccess ||
-      c->cu_count <= 0) {
-    delete c;
-    return ND_E_DEVICE;
-  }
+  if (c->device < 0 || c->device >= ndev)
+    return create_fail(c, ND_E_INVALID_ARG, "device ordinal out of range");
+  if ((e = hipSetDevice(c->device)) != hipSuccess)
+    return create_fail(c, ND_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+  if ((e = hipDeviceGetAttribute(&c->cu_count, hipDeviceAttributeMultiprocessorCount,
+                                 c->device)) != hipSuccess ||
+      c->cu_count <= 0)
+    return create_fail(c, ND_E_DEVICE,
+                       std::string("compute unit count: ") + hipGetErrorString(e));
   int coop = 0;
-  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device) != hipSuccess ||
-      !coop) {
-    delete c;
-    return ND_E_UNSUPPORTED;
-  }
+  if ((e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device)) !=
+          hipSuccess ||
+      !coop)
+    return create_fail(c, ND_E_UNSUPPORTED, "the device does not support cooperative launches");
   c->bufs.resize(B_COUNT);
   c->events_ok = true;
   for (int i = 0; i < 6; i++)

@@ -16,6 +16,11 @@ from dataclasses import dataclass
 
 import numpy as np
 
+try:  # load PyTorch's HIP runtime first: the library runs on that one
+    import torch  # noqa: F401
+except ImportError:  # pragma: no cover - torch is part of the image
+    torch = None
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnucleus.so")
 
@@ -142,11 +147,7 @@ def _ptr(a) -> tuple[int, int]:
 
 
 def _current_stream(device: int):
-    try:
-        import torch
-    except ImportError:  # pragma: no cover - torch is part of the image
-        return None
-    if not torch.cuda.is_available():
+    if torch is None or not torch.cuda.is_available():
         return None
     return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
@@ -183,7 +184,8 @@ class Context:
         h = C.c_void_p()
         st = self.lib.nd_create(C.byref(h), C.byref(opt))
         if st != ND_OK:
-            raise NucleusError(st, self.lib.nd_status_str(st).decode())
+            msg = self.lib.nd_last_error(None).decode() or self.lib.nd_status_str(st).decode()
+            raise NucleusError(st, msg)
         self.h = h
         self.r = self.s = 0
 
