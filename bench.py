@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Benchmark: exact (3,4) nucleus decomposition + hierarchy on one MI355X.
+
+Workload: R-MAT scale 18 (262,144 vertices), edge factor 16,
+(a,b,c,d) = (0.57, 0.19, 0.19, 0.05), seed 2, symmetrised and deduplicated;
+(r,s) = (3,4). A step is one full decomposition from the CSR already resident
+in HBM: orientation, triangle tables, 4-clique counting, the peel rounds with
+hierarchy linking, and the canonical tree.
+
+Metric: s-cliques traversed per second, where a decomposition traverses
+n_s + C(s,r) * n_s s-cliques (each s-clique once while counting, and once per
+member r-clique while peeling). The same numerator is used for the CPU
+oracle baseline, which runs on a smaller R-MAT of the same generator.
+
+Prints one JSON line (see the keys below).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from math import comb
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes of the dominant kernels ("Roofline"):
+#   peel+link kernel: bytes per (r-clique, s-clique) visit and per peeled
+#   r-clique; counting kernel: bytes per listed s-clique.
+PEEL_BYTES_PER_VISIT = {(1, 2): 16, (2, 3): 32, (3, 4): 60}
+PEEL_BYTES_PER_RCLIQUE = {(1, 2): 20, (2, 3): 24, (3, 4): 28}
+COUNT_BYTES_PER_SCLIQUE = {(1, 2): 0, (2, 3): 36, (3, 4): 64}
+
+
+def workload(name: str):
+    from paper_2306_08623_amd import inputs as I
+    if name == "rmat18":
+        return I.workload_rmat18(), "R-MAT scale 18, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), seed 2"
+    if name == "er2k":
+        return I.workload_er2k(), "G(2000, 0.01) + 20 planted cliques of size 5..30, seed 1"
+    if name.startswith("rmat"):
+        sc = int(name[4:])
+        return I.rmat(sc, 16, 2), f"R-MAT scale {sc}, edge factor 16, seed 2"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(r: int, s: int, scale: int) -> dict:
+    """The oracle, single-threaded, on R-MAT at a smaller scale (same
+    generator parameters and seed): traversals per second."""
+    import oracle
+    from paper_2306_08623_amd import inputs as I
+    g = I.rmat(scale, 16, 2)
+    t0 = time.perf_counter()
+    d = oracle.decompose(g, r, s)
+    dt = time.perf_counter() - t0
+    trav = d.n_s + comb(s, r) * d.n_s
+    return {
+        "value": trav / dt,
+        "unit": "s-cliques traversed/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"full ({r},{s}) decomposition of R-MAT scale {scale} (n={g.n}, m={g.m}, "
+                   f"n_r={d.n_r}, n_s={d.n_s}) with the same generator and seed, "
+                   f"{dt:.1f} s on one host core"),
+        "seconds": dt,
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rmat18")
+    ap.add_argument("--rs", default="3,4")
+    ap.add_argument("--cpu-scale", type=int, default=12,
+                    help="R-MAT scale of the oracle baseline sample (0: skip)")
+    ap.add_argument("--peel-blocks", type=int, default=0)
+    ap.add_argument("--verbose", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: the decomposition of one graph is not "
+              "sharded across GPUs in this build (see DESIGN.md, 'Sharding').", file=sys.stderr)
+        return 2
+    r, s = (int(x) for x in args.rs.split(","))
+
+    import torch
+
+    from paper_2306_08623_amd import nucleus
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    g, desc = workload(args.workload)
+    print(f"[bench] {desc}: n={g.n} m={g.m} (r,s)=({r},{s})", file=sys.stderr, flush=True)
+    ctx = nucleus.Context(device=0, peel_blocks=args.peel_blocks)
+    ctx.load_csr(g)              # host -> HBM once; not timed
+    ctx.nd_set_rs(r, s)
+    for i in range(args.warmup):
+        tw = time.perf_counter()
+        ctx.nd_decompose()
+        print(f"[bench] warmup {i}: {time.perf_counter() - tw:.3f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ctx.nd_decompose()
+        infos.append(ctx.nd_get_info())
+        print(f"[bench] step {i}: {time.perf_counter() - t0:.3f} s cumulative", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    info = infos[-1]
+    n_s = info["n_s"]
+    trav = n_s + comb(s, r) * n_s
+    value = trav * args.steps / wall
+    ms_step = 1000.0 * wall / args.steps
+
+    # roofline of the dominant kernel, timed with HIP events on the
+    # library's stream around each launch
+    peel_ms = sum(i["ms_peel_kernel"] for i in infos) / len(infos)
+    count_ms = sum(i["ms_count_kernel"] for i in infos) / len(infos)
+    peel_bytes = (PEEL_BYTES_PER_VISIT[(r, s)] * info["visits"]
+                  + PEEL_BYTES_PER_RCLIQUE[(r, s)] * info["n_r"])
+    count_bytes = COUNT_BYTES_PER_SCLIQUE[(r, s)] * n_s
+    if peel_ms >= count_ms:
+        kname, kms, kbytes = "k_peel", peel_ms, peel_bytes
+    else:
+        kname, kms, kbytes = "k_count_s4" if s == 4 else "k_count_s3", count_ms, count_bytes
+    achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
+    roof = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 2),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "traffic": None, "bytes_per_launch": kbytes, "kernel_ms": round(kms, 4)}
+
+    out = {
+        "metric": f"({r},{s})-nucleus s-cliques traversed/s",
+        "value": value,
+        "unit": "s-cliques traversed/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"{desc}; (r,s)=({r},{s})", "n": g.n, "m": g.m,
+                   "n_r": info["n_r"], "n_s": n_s, "k": info["k"], "rounds": info["rounds"],
+                   "n_int": info["n_int"]},
+        "phases_ms": {"prep": round(info["ms_prep"], 3), "count": round(info["ms_count"], 3),
+                      "peel": round(info["ms_peel"], 3), "tree": round(info["ms_tree"], 3)},
+        "counters": {k: info[k] for k in ("visits", "decrements", "links", "unites",
+                                           "bucket_scans", "max_outdeg", "orient_rounds")},
+        "roofline": roof,
+    }
+    if args.cpu_scale:
+        out["cpu_baseline"] = cpu_baseline(r, s, args.cpu_scale)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

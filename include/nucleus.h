@@ -95,6 +95,8 @@ typedef struct nd_info {
   float ms_count;         /* device time: s-clique counting                   */
   float ms_peel;          /* device time: peel + link rounds                  */
   float ms_tree;          /* device time: tree construction + canonical form  */
+  float ms_count_kernel;  /* device time of the s-clique counting kernel      */
+  float ms_peel_kernel;   /* device time of the persistent peel+link kernel   */
   uint64_t device_bytes;  /* workspace bytes held by the context              */
 } nd_info;
 

@@ -136,7 +136,7 @@ nd_status nd_create(nd_ctx **out, const nd_options *opt) {
     return create_fail(c, ND_E_UNSUPPORTED, "the device does not support cooperative launches");
   c->bufs.resize(B_COUNT);
   c->events_ok = true;
-  for (int i = 0; i < 6; i++)
+  for (int i = 0; i < 10; i++)
     if (hipEventCreate(&c->ev[i]) != hipSuccess) c->events_ok = false;
   nd_status st;
   if (!nd_buf(c, B_SCAL, sizeof(DevScalars), &st)) {
@@ -153,7 +153,7 @@ void nd_destroy(nd_ctx *c) {
   (void)hipStreamSynchronize(c->stream);
   for (auto &b : c->bufs)
     if (b.p) (void)hipFree(b.p);
-  for (int i = 0; i < 6; i++)
+  for (int i = 0; i < 10; i++)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   delete c;
 }
@@ -280,6 +280,10 @@ nd_status nd_decompose(nd_ctx *c) {
     if (hipEventElapsedTime(&ms, c->ev[1], c->ev[2]) == hipSuccess) I.ms_count = ms;
     if (hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) I.ms_peel = ms;
     if (hipEventElapsedTime(&ms, c->ev[3], c->ev[4]) == hipSuccess) I.ms_tree = ms;
+    if (c->n_r && hipEventElapsedTime(&ms, c->ev[5], c->ev[6]) == hipSuccess)
+      I.ms_peel_kernel = ms;
+    if (c->s > 2 && c->m && hipEventElapsedTime(&ms, c->ev[7], c->ev[8]) == hipSuccess)
+      I.ms_count_kernel = ms;
     (void)hipGetLastError();
   }
   c->decomposed = true;

@@ -197,6 +197,7 @@ nd_status nd_stage_count(nd_ctx *c, const GraphView &g) {
     if (st != ND_OK) return st;
   }
   const uint32_t r = c->r, s = c->s;
+  if (c->events_ok) (void)hipEventRecord(c->ev[7], c->stream);
   if (s == 2) {
     if (g.n)
       hipLaunchKernelGGL(k_count_degree, dim3(nd_grid(g.n, 256, 8192)), dim3(256), 0, c->stream,
@@ -224,6 +225,7 @@ nd_status nd_stage_count(nd_ctx *c, const GraphView &g) {
       hipLaunchKernelGGL(k_count_s4<3>, dim3(grid), dim3(kCountBlock), 0, c->stream, g, cnt, sc);
   }
   st = nd_hip(c, hipGetLastError(), "count kernels");
+  if (c->events_ok) (void)hipEventRecord(c->ev[8], c->stream);
   if (st != ND_OK) return st;
   if (nr)
     st = nd_hip(c, hipMemcpyAsync(cnt0, cnt, nr * 4, hipMemcpyDeviceToDevice, c->stream),

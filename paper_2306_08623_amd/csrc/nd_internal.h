@@ -212,8 +212,9 @@ struct nd_ctx {
   uint64_t n_r = 0;
   uint64_t n_int = 0;
 
-  // events for phase timing
-  hipEvent_t ev[6] = {};
+  // events for phase timing: 0 start, 1 prep, 2 count, 3 peel, 4 tree;
+  // 5/6 around the peel kernel, 7/8 around the count kernel
+  hipEvent_t ev[10] = {};
   bool events_ok = false;
 };
 

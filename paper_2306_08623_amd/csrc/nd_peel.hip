@@ -75,15 +75,16 @@ __device__ __forceinline__ uint32_t uf_find(uint32_t *uf, uint32_t x) {
   }
 }
 
-// Joins the sets of a and b; the smaller root id survives. True if this call
-// performed the union.
-__device__ __forceinline__ bool uf_unite(uint32_t *uf, uint32_t a, uint32_t b) {
+// Joins the sets of a and b; the smaller root id survives. Returns the root
+// whose parent pointer this call changed (the loser), or ND_NONE when a and b
+// were already in one set.
+__device__ __forceinline__ uint32_t uf_unite(uint32_t *uf, uint32_t a, uint32_t b) {
   for (;;) {
     a = uf_find(uf, a);
     b = uf_find(uf, b);
-    if (a == b) return false;
+    if (a == b) return ND_NONE;
     if (a > b) { uint32_t t = a; a = b; b = t; }
-    if (cas32(&uf[b], b, a)) return true;
+    if (cas32(&uf[b], b, a)) return b;
   }
 }
 
@@ -148,30 +149,39 @@ __device__ void link_efficient(LinkCtx &c, uint32_t R0, uint32_t Q0) {
     const uint32_t ndR = c.nd[R];
     if (ndR == c.nd[Q]) {
       if (R == Q) continue;
-      if (uf_unite(c.uf, R, Q)) c.unites++;
-      // the root that lost its role hands its nearest-lower-core link to the
-      // surviving root
-      uint32_t pR = uf_find(c.uf, R);
-      if (pR != R) push(ld_acq32(&c.L[R]), pR);
-      uint32_t pQ = uf_find(c.uf, Q);
-      if (pQ != Q) push(ld_acq32(&c.L[Q]), pQ);
+      // The root that lost its role hands its nearest-lower-core link to the
+      // merged set. The loser is the root whose parent this unite changed:
+      // R or Q may have been merged elsewhere after they were read, in which
+      // case unite joins their current roots, and it is one of those whose L
+      // must move (a CAS on L[loser] that lands after this read is handed
+      // over by its own writer, which then sees loser is no longer a root).
+      const uint32_t loser = uf_unite(c.uf, R, Q);
+      if (loser != ND_NONE) {
+        c.unites++;
+        const uint32_t w = uf_find(c.uf, loser);
+        push(ld_acq32(&c.L[loser]), w);
+      }
     } else {
       // ND[R] < ND[Q]: R may become Q's nearest lower core, and R must be
       // connected with Q's current nearest lower core
+      // (L[Q] is read at Q's current root; a CAS is only tried when its
+      // expected value was just observed, since L never returns to empty)
       uint32_t spins = 0;
       for (;;) {
         if (++spins > kLinkStepCap) {
           atomicOr(&c.sc->status, ND_DERR_WATCHDOG);
           return;
         }
-        const uint32_t LQ = ld_acq32(&c.L[Q]);
         Q = uf_find(c.uf, Q);
-        if (cas32(&c.L[Q], ND_NONE, R)) {
-          uint32_t pQ = uf_find(c.uf, Q);
-          if (pQ != Q) push(R, pQ);   // Q was merged meanwhile
-          break;
+        const uint32_t LQ = ld_acq32(&c.L[Q]);
+        if (LQ == ND_NONE) {
+          if (cas32(&c.L[Q], ND_NONE, R)) {
+            uint32_t pQ = uf_find(c.uf, Q);
+            if (pQ != Q) push(R, pQ);   // Q was merged meanwhile
+            break;
+          }
+          continue;                      // L[Q] was set concurrently: read again
         }
-        if (LQ == ND_NONE) continue;  // L[Q] was set concurrently: read again
         if (c.nd[LQ] < ndR) {
           if (cas32(&c.L[Q], LQ, R)) {
             uint32_t pQ = uf_find(c.uf, Q);
@@ -272,6 +282,88 @@ struct Shape<3, 4> {
 };
 
 // ---------------------------------------------------------------------------
+// wave-level link ordering
+// ---------------------------------------------------------------------------
+
+// The link calls of one wave (at most NO per lane) are gathered in LDS,
+// sorted by (frontier r-clique R, core number of the partner R') and issued
+// in that order, one lane per distinct R. Linking the partners of R in
+// ascending core order keeps every cascade short: each new partner only has
+// to descend from the previous partner's level instead of from R's top.
+// The calls themselves are exactly the link(R', R) calls of Algorithm 3; only
+// their order changes, and Algorithm 5 accepts concurrent calls in any order.
+// staging slots per wave: 64 * NO rounded up to a power of two (bitonic sort)
+__host__ __device__ constexpr uint32_t lk_cap(int no) {
+  return no <= 1 ? 64u : (no == 2 ? 128u : 256u);
+}
+
+template <int NO>
+__device__ void wave_link_sorted(LinkCtx &lc, uint64_t *key, uint32_t *val,
+                                 const uint64_t *my_key, const uint32_t *my_val, uint32_t my_n) {
+  constexpr uint32_t CAP = lk_cap(NO);
+  static_assert(CAP >= 64 * NO, "staging too small");
+  const uint32_t lane = lane_id();
+  const uint32_t incl = wave_incl_scan(my_n);
+  const uint32_t total = __shfl(incl, 63, 64);
+  if (total == 0) return;
+  uint32_t pos = incl - my_n;
+#pragma unroll
+  for (int j = 0; j < NO; j++) {
+    if ((uint32_t)j < my_n) {
+      key[pos + j] = my_key[j];
+      val[pos + j] = my_val[j];
+    }
+  }
+  uint32_t N = 1;
+  while (N < total) N <<= 1;
+  for (uint32_t i = total + lane; i < N; i += 64) {
+    key[i] = ~0ull;
+    val[i] = ND_NONE;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // bitonic sort of key[0..N) (N <= CAP, a power of two)
+  for (uint32_t kk = 2; kk <= N; kk <<= 1) {
+    for (uint32_t jj = kk >> 1; jj > 0; jj >>= 1) {
+      for (uint32_t i = lane; i < N; i += 64) {
+        const uint32_t l = i ^ jj;
+        if (l > i) {
+          const uint64_t ki = key[i], kl = key[l];
+          const bool up = (i & kk) == 0;
+          if ((ki > kl) == up) {
+            key[i] = kl;
+            key[l] = ki;
+            const uint32_t vi = val[i];
+            val[i] = val[l];
+            val[l] = vi;
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+  // one lane per run of equal R: link its partners in ascending core order
+  for (uint32_t i = lane; i < total; i += 64) {
+    const uint32_t R = (uint32_t)(key[i] >> 32);
+    if (i > 0 && (uint32_t)(key[i - 1] >> 32) == R) continue;
+    uint32_t prev = ND_NONE;
+    for (uint32_t e = i; e < total && (uint32_t)(key[e] >> 32) == R; e++) {
+      const uint32_t Rp = val[e];
+      if (Rp == prev) continue;   // same partner through another s-clique
+      prev = Rp;
+      link_efficient(lc, Rp, R);
+    }
+  }
+  (void)CAP;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---------------------------------------------------------------------------
 // the persistent kernel
 // ---------------------------------------------------------------------------
 
@@ -282,6 +374,9 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
   __shared__ uint64_t s_boff[kMaxPeelBlocks + 1];
   __shared__ uint32_t s_red[kPeelBlock / 64];
   __shared__ uint64_t s_red64[kPeelBlock / 64];
+  constexpr uint32_t LK = lk_cap(NO);
+  __shared__ uint64_t s_lk_key[kPeelBlock / 64][LK];
+  __shared__ uint32_t s_lk_val[kPeelBlock / 64][LK];
 
   DevScalars *sc = a.sc;
   const GraphView &g = a.g;
@@ -435,6 +530,9 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
       const uint64_t p = base + lane;
       uint32_t others[NO];
       bool push[NO];
+      uint64_t lk_key[NO];
+      uint32_t lk_val[NO];
+      uint32_t nlk = 0;
 #pragma unroll
       for (int j = 0; j < NO; j++) push[j] = false;
       if (p < P) {
@@ -479,7 +577,11 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
           }
 #pragma unroll
           for (int j = 0; j < NO; j++) {
-            if (rr[j] < t || (rr[j] == t && R < others[j])) link_efficient(lc, others[j], R);
+            if (rr[j] < t || (rr[j] == t && R < others[j])) {
+              lk_key[nlk] = ((uint64_t)R << 32) | a.cnt[others[j]];
+              lk_val[nlk] = others[j];
+              nlk++;
+            }
           }
         }
       }
@@ -488,6 +590,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
         uint32_t slot = wave_append(&sc->fsize[(t + 1) & 1], push[j]);
         if (push[j]) Fn[slot] = others[j];
       }
+      wave_link_sorted<NO>(lc, s_lk_key[wv], s_lk_val[wv], lk_key, lk_val, nlk);
     }
     if (!grid_barrier(&sc->barrier, nb, &sc->status)) break;
 
@@ -548,9 +651,12 @@ nd_status launch_peel(nd_ctx *c, PeelArgs &pa) {
   uint32_t nb = (uint32_t)std::max<uint64_t>(1, std::min(want, cap));
   pa.nblocks = nb;
   void *args[] = {&pa};
-  return nd_hip(c, hipLaunchCooperativeKernel(kern, dim3(nb), dim3(kPeelBlock), args, 0,
-                                              c->stream),
-                "peel launch");
+  if (c->events_ok) (void)hipEventRecord(c->ev[5], c->stream);
+  nd_status st = nd_hip(c, hipLaunchCooperativeKernel(kern, dim3(nb), dim3(kPeelBlock), args, 0,
+                                                      c->stream),
+                        "peel launch");
+  if (c->events_ok) (void)hipEventRecord(c->ev[6], c->stream);
+  return st;
 }
 
 }  // namespace

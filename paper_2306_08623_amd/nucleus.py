@@ -80,6 +80,8 @@ class Info(C.Structure):
         ("ms_count", C.c_float),
         ("ms_peel", C.c_float),
         ("ms_tree", C.c_float),
+        ("ms_count_kernel", C.c_float),
+        ("ms_peel_kernel", C.c_float),
         ("device_bytes", C.c_uint64),
     ]
 

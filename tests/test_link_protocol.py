@@ -1,0 +1,254 @@
+"""Host model of the device link protocol, run under random interleavings.
+
+The GPU peels r-cliques in rounds and, inside each round, runs many
+LINK-EFFICIENT calls (Algorithm 5, Section 7.3) concurrently. This test
+replays the same rounds on the CPU with a model of the device routine
+(uf_find with path halving, uf_unite by root index returning the root it
+demoted, the compare-and-swaps on L, the cascade stack) in which every shared
+memory access is a scheduling point, and lets a seeded random scheduler
+interleave the calls of each round. The canonical tree built from the final
+uf and L must equal the oracle's, whatever the interleaving.
+
+It pins the hand-over rule for L after a union: the demoted root is the one
+whose parent the union changed, which can differ from the roots a call read
+at its start (the regression case below failed with the rule that looked at
+those).
+"""
+import random
+
+import pytest
+
+import brute
+import oracle
+from paper_2306_08623_amd import inputs as I
+
+NONE = -1
+
+
+class Mem:
+    def __init__(self, n):
+        self.uf = list(range(n))
+        self.L = [NONE] * n
+
+
+def find(mem, x):
+    while True:
+        p = mem.uf[x]; yield
+        if p == x:
+            return x
+        gp = mem.uf[p]; yield
+        if gp == p:
+            return p
+        if mem.uf[x] == p:
+            mem.uf[x] = gp
+        yield
+        x = gp
+
+
+def unite(mem, a, b):
+    while True:
+        a = yield from find(mem, a)
+        b = yield from find(mem, b)
+        if a == b:
+            return None
+        if a > b:
+            a, b = b, a
+        if mem.uf[b] == b:
+            mem.uf[b] = a
+            yield
+            return b
+        yield
+
+
+def link(mem, nd, R0, Q0):
+    stack = [(R0, Q0)]
+    while stack:
+        R, Q = stack.pop()
+        if R == NONE or Q == NONE:
+            continue
+        if nd[Q] < nd[R]:
+            R, Q = Q, R
+        R = yield from find(mem, R)
+        Q = yield from find(mem, Q)
+        ndR = nd[R]
+        if ndR == nd[Q]:
+            if R == Q:
+                continue
+            loser = yield from unite(mem, R, Q)
+            if loser is not None:
+                w = yield from find(mem, loser)
+                ll = mem.L[loser]; yield
+                stack.append((ll, w))
+        else:
+            while True:
+                Q = yield from find(mem, Q)
+                LQ = mem.L[Q]; yield
+                if LQ == NONE:
+                    if mem.L[Q] == NONE:
+                        mem.L[Q] = R; yield
+                        pQ = yield from find(mem, Q)
+                        if pQ != Q:
+                            stack.append((R, pQ))
+                        break
+                    yield
+                    continue
+                if nd[LQ] < ndR:
+                    if mem.L[Q] == LQ:
+                        mem.L[Q] = R; yield
+                        pQ = yield from find(mem, Q)
+                        if pQ != Q:
+                            stack.append((R, pQ))
+                        stack.append((R, LQ))
+                        break
+                    yield
+                else:
+                    stack.append((R, LQ))
+                    break
+
+
+def run_interleaved(gens, rng):
+    live = list(gens)
+    while live:
+        i = rng.randrange(len(live))
+        try:
+            next(live[i])
+        except StopIteration:
+            live.pop(i)
+
+
+def peel_rounds(n_r, members, cnt0):
+    """Parallel rounds exactly as the kernel: returns nd, list of rounds with
+    the link pairs (R', R) emitted."""
+    inc = [[] for _ in range(n_r)]
+    for si, ids in enumerate(members):
+        for x in ids:
+            inc[x].append(si)
+    cnt = list(cnt0)
+    rnd = [None] * n_r
+    nd = [0] * n_r
+    alive = set(range(n_r))
+    k = 0
+    t = 0
+    rounds = []
+    F = []
+    while alive or F:
+        if not F:
+            if not alive:
+                break
+            kmin = min(cnt[x] for x in alive)
+            F = [x for x in alive if cnt[x] == kmin]
+            k = kmin
+        for R in F:
+            rnd[R] = t
+            nd[R] = k
+            alive.discard(R)
+        pairs = []
+        nxt = []
+        for R in F:
+            for si in inc[R]:
+                others = [x for x in members[si] if x != R]
+                rr = [rnd[x] for x in others]
+                dead = any(r is not None and r < t for r in rr)
+                lead = not any(r == t and o < R for r, o in zip(rr, others))
+                if not dead and lead:
+                    for o, r in zip(others, rr):
+                        if r is None:
+                            old = cnt[o]
+                            cnt[o] -= 1
+                            if old == k + 1:
+                                nxt.append(o)
+                for o, r in zip(others, rr):
+                    if r is not None and (r < t or (r == t and R < o)):
+                        pairs.append((o, R))
+        rounds.append(pairs)
+        F = nxt
+        t += 1
+    return nd, rounds
+
+
+def tree_from(mem, nd, n_r):
+    def froot(x):
+        while mem.uf[x] != x:
+            x = mem.uf[x]
+        return x
+    root = [froot(x) for x in range(n_r)]
+    sz = [0] * n_r
+    for x in range(n_r):
+        sz[root[x]] += 1
+    npar = [NONE] * n_r
+    nkid = [0] * n_r
+    for x in range(n_r):
+        if root[x] == x and mem.L[x] != NONE:
+            npar[x] = root[mem.L[x]]
+            nkid[npar[x]] += 1
+    kept = [root[c] == c and sz[c] + nkid[c] >= 2 for c in range(n_r)]
+    parent = {}
+    level = {}
+    for x in range(n_r):
+        c = root[x]
+        p = c if kept[c] else npar[c]
+        parent[x] = None if p == NONE else ("n", p)
+    for c in range(n_r):
+        if kept[c]:
+            level[("n", c)] = nd[c]
+            parent[("n", c)] = None if npar[c] == NONE else ("n", npar[c])
+    # map to ints for canonicalize_forest
+    ids = {}
+    nxt = n_r
+    for key in level:
+        ids[key] = nxt
+        nxt += 1
+    par2 = {}
+    for x, p in parent.items():
+        xx = x if isinstance(x, int) else ids[x]
+        par2[xx] = None if p is None else ids[p]
+    lev2 = {ids[k]: v for k, v in level.items()}
+    return brute.canonicalize_forest(n_r, par2, lev2)
+
+
+def check(g, r, s, seed, chunk):
+    """Decompose g with the round model and one random interleaving; compare
+    the canonical tree with the oracle."""
+    adj = brute.adjacency_sets(g)
+    R, S, deg, members = brute.s_clique_degrees(adj, r, s)
+    n_r = len(R)
+    nd, rounds = peel_rounds(n_r, members, deg)
+    d = oracle.decompose(g, r, s)
+    assert nd == d.coreness.tolist()
+    rng = random.Random(seed)
+    mem = Mem(n_r)
+    for pairs in rounds:
+        rng.shuffle(pairs)
+        gens = [link(mem, nd, a, b) for a, b in pairs]
+        run_interleaved(gens, rng)
+    parent, level = tree_from(mem, nd, n_r)
+    ok = parent == d.parent.tolist() and level == d.level.tolist()
+    return ok
+
+
+
+
+@pytest.mark.parametrize("rs", [(1, 2), (2, 3), (3, 4)])
+def test_random_interleavings(rs):
+    r, s = rs
+    for gi in range(150):
+        n = random.Random(gi).randint(6, 26)
+        p = random.Random(gi + 1).uniform(0.15, 0.6)
+        g = I.gnp(n, p, seed=gi)
+        for seed in range(3):
+            assert check(g, r, s, seed, 1), (gi, n, p, rs, seed)
+
+
+def test_regression_stale_root_handover():
+    """8 vertices, (1,2): a union demotes a root that the uniting call never
+    read; its L entry (set concurrently) must still be handed over."""
+    g = I.gnp(8, random.Random(67).uniform(0.15, 0.6), seed=66)
+    for seed in range(40):
+        assert check(g, 1, 2, seed, 1), seed
+
+
+def test_planted_interleavings():
+    g = I.er_planted(40, 0.1, 3, 5, 9, seed=4)
+    for r, s in [(1, 2), (2, 3), (3, 4)]:
+        for seed in range(4):
+            assert check(g, r, s, seed, 1), (r, s, seed)
