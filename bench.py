@@ -157,7 +157,7 @@ def main() -> int:
                    "n_int": info["n_int"]},
         "phases_ms": {"prep": round(info["ms_prep"], 3), "count": round(info["ms_count"], 3),
                       "peel": round(info["ms_peel"], 3), "tree": round(info["ms_tree"], 3)},
-        "counters": {k: info[k] for k in ("visits", "decrements", "links", "unites",
+        "counters": {k: info[k] for k in ("visits", "decrements", "links", "link_calls", "unites",
                                            "bucket_scans", "max_outdeg", "orient_rounds")},
         "roofline": roof,
     }

@@ -86,7 +86,9 @@ typedef struct nd_info {
   uint64_t n_int;         /* internal nodes of the canonical tree             */
   uint64_t visits;        /* (r-clique, s-clique) pairs traversed while peeling */
   uint64_t decrements;    /* count decrements                                 */
-  uint64_t links;         /* link calls (Algorithm 5), cascades included      */
+  uint64_t links;         /* link steps (Algorithm 5 calls, cascades included) */
+  uint64_t link_calls;    /* top-level link calls issued (after skipping pairs
+                             of roots already linked)                         */
   uint64_t unites;        /* successful union-find unions                     */
   uint64_t bucket_scans;  /* scans of the remaining r-cliques for a new k     */
   uint32_t max_outdeg;    /* out-degree bound reached by the orientation      */

@@ -270,6 +270,7 @@ nd_status nd_decompose(nd_ctx *c) {
   I.visits = hs.visits;
   I.decrements = hs.decrements;
   I.links = hs.links;
+  I.link_calls = hs.link_calls;
   I.unites = hs.unites;
   I.bucket_scans = hs.bucket_scans;
   I.orient_rounds = hs.orient_round;

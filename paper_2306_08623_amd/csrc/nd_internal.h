@@ -237,6 +237,7 @@ struct DevScalars {
   uint64_t barrier;        // grid barrier arrivals
   uint64_t visits, decrements, links, unites;
   uint64_t bucket_scans;
+  uint64_t link_calls;     // link calls issued after the redundancy filter
   uint32_t status;         // ND_DERR_* bits
   uint32_t k;              // final level reached
   uint32_t rounds;         // peel rounds executed

@@ -282,85 +282,34 @@ struct Shape<3, 4> {
 };
 
 // ---------------------------------------------------------------------------
-// wave-level link ordering
+// redundant-link filter
 // ---------------------------------------------------------------------------
 
-// The link calls of one wave (at most NO per lane) are gathered in LDS,
-// sorted by (frontier r-clique R, core number of the partner R') and issued
-// in that order, one lane per distinct R. Linking the partners of R in
-// ascending core order keeps every cascade short: each new partner only has
-// to descend from the previous partner's level instead of from R's top.
-// The calls themselves are exactly the link(R', R) calls of Algorithm 3; only
-// their order changes, and Algorithm 5 accepts concurrent calls in any order.
-// staging slots per wave: 64 * NO rounded up to a power of two (bitonic sort)
-__host__ __device__ constexpr uint32_t lk_cap(int no) {
-  return no <= 1 ? 64u : (no == 2 ? 128u : 256u);
+// A block keeps a small LDS table of root pairs (x, q) it has already linked:
+// link(R', R) was completed with find(R') = x and find(R) = q. Union-find
+// roots never become roots again after losing a union and sets only grow, so
+// a later call whose partner and frontier r-clique still have roots x and q
+// adds no information (its partner lies in x's set, which is connected to
+// q's set at x's level) and is skipped. Entries are single 64-bit LDS words,
+// so a lookup never sees half of an entry.
+constexpr uint32_t kLinkCache = 2048;
+
+__device__ __forceinline__ uint32_t lcache_slot(uint32_t x, uint32_t q) {
+  return ((x * 0x9E3779B1u) ^ (q * 0x85EBCA77u) ^ (q >> 15)) & (kLinkCache - 1);
 }
 
-template <int NO>
-__device__ void wave_link_sorted(LinkCtx &lc, uint64_t *key, uint32_t *val,
-                                 const uint64_t *my_key, const uint32_t *my_val, uint32_t my_n) {
-  constexpr uint32_t CAP = lk_cap(NO);
-  static_assert(CAP >= 64 * NO, "staging too small");
-  const uint32_t lane = lane_id();
-  const uint32_t incl = wave_incl_scan(my_n);
-  const uint32_t total = __shfl(incl, 63, 64);
-  if (total == 0) return;
-  uint32_t pos = incl - my_n;
-#pragma unroll
-  for (int j = 0; j < NO; j++) {
-    if ((uint32_t)j < my_n) {
-      key[pos + j] = my_key[j];
-      val[pos + j] = my_val[j];
-    }
-  }
-  uint32_t N = 1;
-  while (N < total) N <<= 1;
-  for (uint32_t i = total + lane; i < N; i += 64) {
-    key[i] = ~0ull;
-    val[i] = ND_NONE;
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  // bitonic sort of key[0..N) (N <= CAP, a power of two)
-  for (uint32_t kk = 2; kk <= N; kk <<= 1) {
-    for (uint32_t jj = kk >> 1; jj > 0; jj >>= 1) {
-      for (uint32_t i = lane; i < N; i += 64) {
-        const uint32_t l = i ^ jj;
-        if (l > i) {
-          const uint64_t ki = key[i], kl = key[l];
-          const bool up = (i & kk) == 0;
-          if ((ki > kl) == up) {
-            key[i] = kl;
-            key[l] = ki;
-            const uint32_t vi = val[i];
-            val[i] = val[l];
-            val[l] = vi;
-          }
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-  }
-  // one lane per run of equal R: link its partners in ascending core order
-  for (uint32_t i = lane; i < total; i += 64) {
-    const uint32_t R = (uint32_t)(key[i] >> 32);
-    if (i > 0 && (uint32_t)(key[i - 1] >> 32) == R) continue;
-    uint32_t prev = ND_NONE;
-    for (uint32_t e = i; e < total && (uint32_t)(key[e] >> 32) == R; e++) {
-      const uint32_t Rp = val[e];
-      if (Rp == prev) continue;   // same partner through another s-clique
-      prev = Rp;
-      link_efficient(lc, Rp, R);
-    }
-  }
-  (void)CAP;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+__device__ __forceinline__ bool lcache_hit(const uint64_t *cache, uint32_t x, uint32_t q) {
+  const uint64_t key = ((uint64_t)x << 32) | q;
+  const uint32_t h = lcache_slot(x, q);
+  return cache[h] == key || cache[h ^ 1] == key;
+}
+
+__device__ __forceinline__ void lcache_put(uint64_t *cache, uint32_t x, uint32_t q) {
+  const uint64_t key = ((uint64_t)x << 32) | q;
+  const uint32_t h = lcache_slot(x, q);
+  // keep the other way of the pair if it already holds this key
+  if (cache[h ^ 1] == key) return;
+  atomicExch((unsigned long long *)&cache[h], (unsigned long long)key);
 }
 
 // ---------------------------------------------------------------------------
@@ -374,9 +323,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
   __shared__ uint64_t s_boff[kMaxPeelBlocks + 1];
   __shared__ uint32_t s_red[kPeelBlock / 64];
   __shared__ uint64_t s_red64[kPeelBlock / 64];
-  constexpr uint32_t LK = lk_cap(NO);
-  __shared__ uint64_t s_lk_key[kPeelBlock / 64][LK];
-  __shared__ uint32_t s_lk_val[kPeelBlock / 64][LK];
+  __shared__ uint64_t s_lcache[kLinkCache];
 
   DevScalars *sc = a.sc;
   const GraphView &g = a.g;
@@ -395,7 +342,9 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
   lc.sc = sc;
   lc.links = 0;
   lc.unites = 0;
-  uint64_t visits = 0, decs = 0, scans = 0;
+  uint64_t visits = 0, decs = 0, scans = 0, calls = 0;
+  for (uint32_t i = threadIdx.x; i < kLinkCache; i += kPeelBlock) s_lcache[i] = ~0ull;
+  __syncthreads();
 
   uint32_t k = 0;
   uint32_t t = 0;
@@ -530,9 +479,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
       const uint64_t p = base + lane;
       uint32_t others[NO];
       bool push[NO];
-      uint64_t lk_key[NO];
-      uint32_t lk_val[NO];
-      uint32_t nlk = 0;
+
 #pragma unroll
       for (int j = 0; j < NO; j++) push[j] = false;
       if (p < P) {
@@ -575,12 +522,16 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
               }
             }
           }
+          uint32_t q = ND_NONE;
 #pragma unroll
           for (int j = 0; j < NO; j++) {
             if (rr[j] < t || (rr[j] == t && R < others[j])) {
-              lk_key[nlk] = ((uint64_t)R << 32) | a.cnt[others[j]];
-              lk_val[nlk] = others[j];
-              nlk++;
+              if (q == ND_NONE) q = uf_find(a.uf, R);
+              const uint32_t x = uf_find(a.uf, others[j]);
+              if (x == q || lcache_hit(s_lcache, x, q)) continue;
+              calls++;
+              link_efficient(lc, others[j], R);
+              lcache_put(s_lcache, x, q);
             }
           }
         }
@@ -590,7 +541,6 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
         uint32_t slot = wave_append(&sc->fsize[(t + 1) & 1], push[j]);
         if (push[j]) Fn[slot] = others[j];
       }
-      wave_link_sorted<NO>(lc, s_lk_key[wv], s_lk_val[wv], lk_key, lk_val, nlk);
     }
     if (!grid_barrier(&sc->barrier, nb, &sc->status)) break;
 
@@ -618,8 +568,9 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
 
   // statistics
   uint64_t v = wave_sum64(visits), d = wave_sum64(decs), l = wave_sum64(lc.links),
-           u = wave_sum64(lc.unites);
+           u = wave_sum64(lc.unites), cl = wave_sum64(calls);
   if (lane == 0) {
+    if (cl) atomicAdd((unsigned long long *)&sc->link_calls, (unsigned long long)cl);
     if (v) atomicAdd((unsigned long long *)&sc->visits, (unsigned long long)v);
     if (d) atomicAdd((unsigned long long *)&sc->decrements, (unsigned long long)d);
     if (l) atomicAdd((unsigned long long *)&sc->links, (unsigned long long)l);

@@ -72,6 +72,7 @@ class Info(C.Structure):
         ("visits", C.c_uint64),
         ("decrements", C.c_uint64),
         ("links", C.c_uint64),
+        ("link_calls", C.c_uint64),
         ("unites", C.c_uint64),
         ("bucket_scans", C.c_uint64),
         ("max_outdeg", C.c_uint32),
