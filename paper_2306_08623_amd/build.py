@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnucleus.so")
+DRIVER = os.path.join(HERE, "nd_profile")
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -37,24 +38,12 @@ def _compile(src: str) -> str:
 
 
 def _runtime_dirs() -> list[str]:
-    """Directories to search for the HIP runtime at load time.
-
-    PyTorch ships its own libamdhip64.so.7 (same SONAME as /opt/rocm's). A
-    process holds only one library per SONAME, so the library must run on
-    the one torch loads; it is searched first, /opt/rocm/lib second.
-    """
-    dirs = []
-    try:
-        import importlib.util
-        spec = importlib.util.find_spec("torch")
-        if spec and spec.origin:
-            tdir = os.path.join(os.path.dirname(spec.origin), "lib")
-            if os.path.exists(os.path.join(tdir, "libamdhip64.so")):
-                dirs.append(tdir)
-    except Exception:
-        pass
-    dirs.append("/opt/rocm/lib")
-    return dirs
+    """Where the HIP runtime is searched at load time when no process-wide
+    copy is loaded yet. PyTorch ships its own libamdhip64.so.7 (same SONAME):
+    the Python binding imports torch before loading this library, so in a
+    torch process the library runs on torch's runtime; a process without
+    torch (the profiling driver) uses /opt/rocm's."""
+    return ["/opt/rocm/lib"]
 
 
 def build(verbose: bool = False) -> str:
@@ -71,8 +60,18 @@ def build(verbose: bool = False) -> str:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc link failed")
     os.replace(tmp, LIB)
+    # profiling driver: the C ABI from a plain C++ program (no Python/torch)
+    drv_tmp = DRIVER + f".tmp{os.getpid()}"
+    cmd = ["g++", "-O2", "-std=c++17", "-I" + os.path.join(os.path.dirname(HERE), "include"),
+           os.path.join(HERE, "nd_profile.cpp"), "-L" + HERE, "-lnucleus",
+           f"-Wl,-rpath,{HERE}:/opt/rocm/lib", "-o", drv_tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("driver build failed")
+    os.replace(drv_tmp, DRIVER)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", DRIVER)
     return LIB
 
 

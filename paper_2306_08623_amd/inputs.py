@@ -428,3 +428,25 @@ def serve_graph(i: int, base_seed: int = 5_000_000, m_lo: int = 1_000,
         scale = max(4, int(round(np.log2(max(2, m / 8)))))
         g = rmat(scale, 8, sub_seed)
     return g, r, s
+
+
+# ---------------------------------------------------------------------------
+# Binary CSR files (for the C++ profiling driver)
+# ---------------------------------------------------------------------------
+
+def save_csr(csr: CSR, path: str) -> None:
+    """uint32 n, uint64 nnz, uint64 row_ptr[n+1], uint32 col[nnz], little endian."""
+    with open(path, "wb") as f:
+        f.write(np.uint32(csr.n).tobytes())
+        f.write(np.uint64(csr.nnz).tobytes())
+        f.write(np.ascontiguousarray(csr.row_ptr, dtype="<u8").tobytes())
+        f.write(np.ascontiguousarray(csr.col, dtype="<u4").tobytes())
+
+
+def load_csr(path: str) -> CSR:
+    with open(path, "rb") as f:
+        n = int(np.frombuffer(f.read(4), dtype="<u4")[0])
+        nnz = int(np.frombuffer(f.read(8), dtype="<u8")[0])
+        rp = np.frombuffer(f.read(8 * (n + 1)), dtype="<u8").astype(np.uint64)
+        col = np.frombuffer(f.read(4 * nnz), dtype="<u4").astype(np.uint32)
+    return CSR(n=n, row_ptr=rp, col=col)
