@@ -86,14 +86,19 @@ template <int R>
 __global__ void __launch_bounds__(kCountBlock) k_count_s4(GraphView g, uint32_t *__restrict__ cnt,
                                                           DevScalars *sc) {
   constexpr uint32_t W = kCountBlock / 64;
+  constexpr uint32_t TC = R == 3 ? kC2Cap : 1;
   __shared__ uint32_t s_v[W][kC2Cap];
   __shared__ uint32_t s_eu[W][kC2Cap];
   __shared__ uint32_t s_ev[W][kC2Cap];
+  __shared__ uint32_t s_t[W][TC];    // r = 3: id of triangle {u, v, w} per C2 entry
+  __shared__ uint32_t s_n[W][TC];    // r = 3: 4-cliques found so far through it
   const uint32_t wv = threadIdx.x / 64;
   const uint32_t lane = lane_id();
   uint32_t *cv = s_v[wv];
   uint32_t *ceu = s_eu[wv];
   uint32_t *cev = s_ev[wv];
+  uint32_t *ct = s_t[wv];
+  uint32_t *cn = s_n[wv];
   uint64_t local = 0;
   const uint64_t nwaves = (uint64_t)gridDim.x * W;
   for (uint64_t j = blockIdx.x * (uint64_t)W + wv; j < g.m; j += nwaves) {
@@ -124,6 +129,10 @@ __global__ void __launch_bounds__(kCountBlock) k_count_s4(GraphView g, uint32_t 
           cv[slot] = w;
           ceu[slot] = e_uw;
           cev[slot] = e_vw;
+          if (R == 3) {
+            ct[slot % TC] = tri_lookup(g, u, v, w, e_uv, e_uw, e_vw);
+            cn[slot % TC] = 0;
+          }
         }
       }
       c += __popcll(mask);
@@ -138,6 +147,7 @@ __global__ void __launch_bounds__(kCountBlock) k_count_s4(GraphView g, uint32_t 
     for (uint32_t a = 0; a + 1 < c; a++) {
       const uint32_t w = cv[a];
       const uint64_t kw = g.okey[w];
+      uint32_t hits_a = 0;   // r = 3: 4-cliques through triangle {u, v, w}
       for (uint32_t b = a + 1 + lane; b < c; b += 64) {
         const uint32_t x = cv[b];
         // adjacency of w and x through the out-row of the lower-key vertex
@@ -160,18 +170,33 @@ __global__ void __launch_bounds__(kCountBlock) k_count_s4(GraphView g, uint32_t 
           atomicAdd(&cnt[cev[b]], 1u);
           atomicAdd(&cnt[g.dge[p]], 1u);
         } else {
+          // triangles {u,v,w} and {u,v,x} are counted per C2 entry (LDS),
+          // {u,w,x} and {v,w,x} per 4-clique
           const uint32_t e_wx = g.dge[p];
-          // triangles {u,v,w} {u,v,x} {u,w,x} {v,w,x}
-          const uint32_t t4[4] = {tri_lookup(g, u, v, w, e_uv, ceu[a], cev[a]),
-                                  tri_lookup(g, u, v, x, e_uv, ceu[b], cev[b]),
-                                  tri_lookup(g, u, w, x, ceu[a], ceu[b], e_wx),
+          hits_a++;
+          atomicAdd(&cn[b % TC], 1u);
+          const uint32_t t2[2] = {tri_lookup(g, u, w, x, ceu[a], ceu[b], e_wx),
                                   tri_lookup(g, v, w, x, cev[a], cev[b], e_wx)};
 #pragma unroll
-          for (int z = 0; z < 4; z++) {
-            if (t4[z] == ND_NONE) atomicOr(&sc->status, ND_DERR_BADGRAPH);
-            else atomicAdd(&cnt[t4[z]], 1u);
+          for (int z = 0; z < 2; z++) {
+            if (t2[z] == ND_NONE) atomicOr(&sc->status, ND_DERR_BADGRAPH);
+            else atomicAdd(&cnt[t2[z]], 1u);
           }
         }
+      }
+      if (R == 3) {
+        hits_a = wave_sum64(hits_a);
+        if (lane == 0 && hits_a) atomicAdd(&cn[a % TC], hits_a);
+      }
+    }
+    if (R == 3) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (uint32_t e = lane; e < c; e += 64) {
+        if (cn[e % TC] == 0) continue;
+        if (ct[e % TC] == ND_NONE) atomicOr(&sc->status, ND_DERR_BADGRAPH);
+        else atomicAdd(&cnt[ct[e % TC]], cn[e % TC]);
       }
     }
     __builtin_amdgcn_wave_barrier();

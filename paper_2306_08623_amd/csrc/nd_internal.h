@@ -9,7 +9,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/nucleus.h"
+#include "nucleus.h"
 
 #define ND_NONE 0xFFFFFFFFu          // empty r-clique id / empty L entry
 #define ND_ALIVE 0xFFFFFFFFu         // peel_round of an unpeeled r-clique
@@ -227,7 +227,7 @@ enum BufId : int {
   B_F0, B_F1, B_WSCAN, B_AL0, B_AL1, B_BTOT, B_LINKQ,
   B_SCAL, B_TMP64, B_TMP32A, B_TMP32B, B_TMP32C, B_TMP32D,
   B_SORTK0, B_SORTK1, B_SORTV0, B_SORTV1, B_HIST,
-  B_PARENT, B_LEVEL, B_RCL,
+  B_PARENT, B_LEVEL, B_RCL, B_GCACHE, B_ACNT,
   B_COUNT
 };
 

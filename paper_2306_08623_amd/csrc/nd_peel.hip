@@ -51,13 +51,17 @@ struct PeelArgs {
   uint32_t *L;        // nearest lower core link of a uf root
   uint32_t *F0, *F1;  // frontiers by round parity
   uint64_t *wscan;    // per frontier slot: inclusive work prefix in its segment
-  uint32_t *al0, *al1;  // remaining r-cliques by scan parity
+  uint32_t *al0, *al1;  // remaining r-cliques by scan parity, one segment per block
+  uint32_t *acnt;       // [2 * nblocks] length of each block's segment list
   uint64_t *btot;     // per block: work total of its frontier segment
   uint32_t *linkq;    // spilled link pairs
   uint32_t linkq_cap;
+  uint64_t *gcache;   // device-wide table of linked root pairs
+  uint64_t gcache_mask;
   DevScalars *sc;
   uint32_t nblocks;
   uint32_t max_rounds;
+  uint32_t chunk;     // probe entries per lane task
 };
 
 // ---------------------------------------------------------------------------
@@ -202,6 +206,27 @@ __device__ void link_efficient(LinkCtx &c, uint32_t R0, uint32_t Q0) {
 // per-(r,s) s-clique discovery around a frontier r-clique
 // ---------------------------------------------------------------------------
 
+// First index >= x in the sorted range a[lo, hi) when the answer is known to
+// be >= lo: doubling steps from lo, then a binary search in the last step.
+// Consecutive probes of one chunk are ascending, so each search starts where
+// the previous one ended.
+__device__ __forceinline__ uint64_t gallop(const uint32_t *a, uint64_t lo, uint64_t hi,
+                                           uint32_t x) {
+  if (lo >= hi || a[lo] >= x) return lo;
+  uint64_t base = lo, step = 1;   // a[base] < x
+  while (base + step < hi && a[base + step] < x) {
+    base += step;
+    step <<= 1;
+  }
+  const uint64_t end = base + step + 1 < hi ? base + step + 1 : hi;
+  return lower_bound_u32<uint64_t>(a, base + 1, end, x);
+}
+
+// Every shape lists, for a frontier r-clique R, its "probe" list (the
+// shortest adjacency-like list whose entries extend R to an s-clique
+// candidate). len() is its length; begin() positions an iterator at probe
+// index i0; step() tests the next probe entry and, when it closes an
+// s-clique, writes the ids of the other r-cliques of that s-clique.
 template <int R_, int S_>
 struct Shape;
 
@@ -209,11 +234,17 @@ struct Shape;
 template <>
 struct Shape<1, 2> {
   static constexpr int kOthers = 1;
-  __device__ static uint32_t work(const GraphView &g, uint32_t R) {
+  struct It {
+    uint64_t sp;
+  };
+  __device__ static uint32_t len(const GraphView &g, uint32_t R) {
     return (uint32_t)(g.rp[R + 1] - g.rp[R]);
   }
-  __device__ static bool visit(const GraphView &g, uint32_t R, uint32_t i, uint32_t *o) {
-    o[0] = g.col[g.rp[R] + i];
+  __device__ static void begin(const GraphView &g, uint32_t R, uint32_t i0, It &it) {
+    it.sp = g.rp[R] + i0;
+  }
+  __device__ static bool step(const GraphView &g, It &it, uint32_t *o) {
+    o[0] = g.col[it.sp++];
     return true;
   }
 };
@@ -223,21 +254,28 @@ struct Shape<1, 2> {
 template <>
 struct Shape<2, 3> {
   static constexpr int kOthers = 2;
-  __device__ static uint32_t work(const GraphView &g, uint32_t R) {
+  struct It {
+    uint64_t sp, sq, eq;
+  };
+  __device__ static uint32_t len(const GraphView &g, uint32_t R) {
     const uint32_t u = g.eu[R], v = g.ev[R];
     const uint64_t du = g.rp[u + 1] - g.rp[u], dv = g.rp[v + 1] - g.rp[v];
     return (uint32_t)(du < dv ? du : dv);
   }
-  __device__ static bool visit(const GraphView &g, uint32_t R, uint32_t i, uint32_t *o) {
+  __device__ static void begin(const GraphView &g, uint32_t R, uint32_t i0, It &it) {
     uint32_t p = g.eu[R], q = g.ev[R];
     if (g.rp[q + 1] - g.rp[q] < g.rp[p + 1] - g.rp[p]) { uint32_t t = p; p = q; q = t; }
-    const uint64_t sp = g.rp[p] + i;
+    it.sp = g.rp[p] + i0;
+    it.sq = g.rp[q];
+    it.eq = g.rp[q + 1];
+  }
+  __device__ static bool step(const GraphView &g, It &it, uint32_t *o) {
+    const uint64_t sp = it.sp++;
     const uint32_t x = g.col[sp];
-    const uint64_t bq = g.rp[q], eq = g.rp[q + 1];
-    const uint64_t sq = find_u32<uint64_t>(g.col, bq, eq, x);
-    if (sq == eq) return false;
+    it.sq = gallop(g.col, it.sq, it.eq, x);
+    if (it.sq == it.eq || g.col[it.sq] != x) return false;
     o[0] = g.eid[sp];
-    o[1] = g.eid[sq];
+    o[1] = g.eid[it.sq];
     return true;
   }
 };
@@ -248,7 +286,10 @@ struct Shape<2, 3> {
 template <>
 struct Shape<3, 4> {
   static constexpr int kOthers = 3;
-  __device__ static uint32_t work(const GraphView &g, uint32_t R) {
+  struct It {
+    uint64_t p0, p1, f1, p2, f2;
+  };
+  __device__ static uint32_t len(const GraphView &g, uint32_t R) {
     const uint32_t e0 = g.te[3ull * R], e1 = g.te[3ull * R + 1], e2 = g.te[3ull * R + 2];
     uint64_t s0 = g.wp[e0 + 1] - g.wp[e0], s1 = g.wp[e1 + 1] - g.wp[e1],
              s2 = g.wp[e2 + 1] - g.wp[e2];
@@ -256,7 +297,7 @@ struct Shape<3, 4> {
     mn = mn < s2 ? mn : s2;
     return (uint32_t)mn;
   }
-  __device__ static bool visit(const GraphView &g, uint32_t R, uint32_t i, uint32_t *o) {
+  __device__ static void begin(const GraphView &g, uint32_t R, uint32_t i0, It &it) {
     uint32_t e0 = g.te[3ull * R], e1 = g.te[3ull * R + 1], e2 = g.te[3ull * R + 2];
     uint64_t s0 = g.wp[e0 + 1] - g.wp[e0], s1 = g.wp[e1 + 1] - g.wp[e1],
              s2 = g.wp[e2 + 1] - g.wp[e2];
@@ -266,17 +307,22 @@ struct Shape<3, 4> {
     } else if (s2 < s0 && s2 < s1) {
       uint32_t t = e0; e0 = e2; e2 = t;
     }
-    const uint64_t p0 = g.wp[e0] + i;
+    it.p0 = g.wp[e0] + i0;
+    it.p1 = g.wp[e1];
+    it.f1 = g.wp[e1 + 1];
+    it.p2 = g.wp[e2];
+    it.f2 = g.wp[e2 + 1];
+  }
+  __device__ static bool step(const GraphView &g, It &it, uint32_t *o) {
+    const uint64_t p0 = it.p0++;
     const uint32_t x = g.wc[p0];
-    const uint64_t b1 = g.wp[e1], f1 = g.wp[e1 + 1];
-    const uint64_t p1 = find_u32<uint64_t>(g.wc, b1, f1, x);
-    if (p1 == f1) return false;
-    const uint64_t b2 = g.wp[e2], f2 = g.wp[e2 + 1];
-    const uint64_t p2 = find_u32<uint64_t>(g.wc, b2, f2, x);
-    if (p2 == f2) return false;
+    it.p1 = gallop(g.wc, it.p1, it.f1, x);
+    if (it.p1 == it.f1 || g.wc[it.p1] != x) return false;
+    it.p2 = gallop(g.wc, it.p2, it.f2, x);
+    if (it.p2 == it.f2 || g.wc[it.p2] != x) return false;
     o[0] = g.wt[p0];
-    o[1] = g.wt[p1];
-    o[2] = g.wt[p2];
+    o[1] = g.wt[it.p1];
+    o[2] = g.wt[it.p2];
     return true;
   }
 };
@@ -312,6 +358,28 @@ __device__ __forceinline__ void lcache_put(uint64_t *cache, uint32_t x, uint32_t
   atomicExch((unsigned long long *)&cache[h], (unsigned long long)key);
 }
 
+// Second level: a lossy device-wide table of the same pairs (2^k entries,
+// cleared per decomposition). Every key ever stored names a completed link,
+// so a lookup may use plain (possibly stale) loads: an old word is either
+// empty (a miss, costing one redundant link) or another valid pair.
+__device__ __forceinline__ uint64_t gcache_slot(uint32_t x, uint32_t q, uint64_t mask) {
+  uint64_t h = ((uint64_t)x * 0x9E3779B97F4A7C15ull) ^ ((uint64_t)q * 0xC2B2AE3D27D4EB4Full);
+  return (h >> 17) & mask;
+}
+
+// Root of x from plain loads, without compression. Parent pointers only
+// ever point to smaller ids, so the walk ends even on stale values, and any
+// node it returns was, at some time, a root whose set contained x (so x is
+// connected to it at their common core number). Used only to form cache
+// keys, where such an ancestor is as good as the current root.
+__device__ __forceinline__ uint32_t key_root(const uint32_t *uf, uint32_t x) {
+  for (;;) {
+    const uint32_t p = uf[x];
+    if (p == x) return x;
+    x = p;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // the persistent kernel
 // ---------------------------------------------------------------------------
@@ -322,6 +390,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
   constexpr int NO = Sh::kOthers;
   __shared__ uint64_t s_boff[kMaxPeelBlocks + 1];
   __shared__ uint32_t s_red[kPeelBlock / 64];
+  __shared__ uint32_t s_cnt[kPeelBlock / 64];
   __shared__ uint64_t s_red64[kPeelBlock / 64];
   __shared__ uint64_t s_lcache[kLinkCache];
 
@@ -346,9 +415,10 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
   for (uint32_t i = threadIdx.x; i < kLinkCache; i += kPeelBlock) s_lcache[i] = ~0ull;
   __syncthreads();
 
+  const uint32_t C = a.chunk;   // probe entries per lane task
   uint32_t k = 0;
   uint32_t t = 0;
-  uint32_t q = 0;   // bucket scans done
+  uint32_t nscan = 0;   // bucket scans done
   bool done = false;
 
   while (!done) {
@@ -361,26 +431,45 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
     uint32_t f = ld_acq32(&sc->fsize[t & 1]);
 
     if (f == 0) {
-      // ---- bucket scan: new level = minimum count of the remaining r-cliques
-      const uint32_t qp = q & 1;
-      const uint32_t *in = qp ? a.al1 : a.al0;
-      uint32_t *out = qp ? a.al0 : a.al1;
-      const uint64_t nin = (q == 0) ? a.n_r : ld_acq32(&sc->n_alive[qp]);
+      // ---- bucket scan: new level = minimum count of the remaining r-cliques.
+      // Every workgroup owns one segment of the id range and keeps the list
+      // of its still-present r-cliques compacted in place (order preserved),
+      // so a scan needs one global atomic per workgroup, not per wave.
+      const uint32_t qp = nscan & 1;
+      const uint64_t bseg = (a.n_r + nb - 1) / nb;
+      const uint64_t rbeg = min64((uint64_t)blockIdx.x * bseg, a.n_r);
+      const uint32_t *in = (qp ? a.al1 : a.al0) + rbeg;
+      uint32_t *out = (qp ? a.al0 : a.al1) + rbeg;
+      const uint32_t nin = (nscan == 0) ? (uint32_t)(min64(rbeg + bseg, a.n_r) - rbeg)
+                                        : a.acnt[qp * nb + blockIdx.x];
       uint32_t mn = ND_NONE;
-      for (uint64_t base = blockIdx.x * (uint64_t)kPeelBlock; base < nin; base += nthreads) {
-        const uint64_t i = base + threadIdx.x;
+      uint32_t nkeep = 0;
+      for (uint32_t base = 0; base < nin; base += kPeelBlock) {
+        const uint32_t i = base + threadIdx.x;
         bool keep = false;
         uint32_t id = 0;
         if (i < nin) {
-          id = (q == 0) ? (uint32_t)i : in[i];
+          id = (nscan == 0) ? (uint32_t)(rbeg + i) : in[i];
           if (a.round[id] == ND_ALIVE) {
             keep = true;
             uint32_t cv = a.cnt[id];
             mn = cv < mn ? cv : mn;
           }
         }
-        uint32_t slot = wave_append(&sc->n_alive[qp ^ 1], keep);
-        if (keep) out[slot] = id;
+        const uint64_t m = ballot64(keep);
+        if (lane == 0) s_cnt[wv] = __popcll(m);
+        __syncthreads();
+        uint32_t woff = 0, tot = 0;
+        for (uint32_t w = 0; w < kPeelBlock / 64; w++) {
+          woff += w < wv ? s_cnt[w] : 0;
+          tot += s_cnt[w];
+        }
+        if (keep) {
+          const uint64_t below = m & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)));
+          out[nkeep + woff + __popcll(below)] = id;
+        }
+        nkeep += tot;
+        __syncthreads();
       }
       mn = wave_min32(mn);
       if (lane == 0) s_red[wv] = mn;
@@ -389,6 +478,8 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
         uint32_t bm = ND_NONE;
         for (uint32_t w = 0; w < kPeelBlock / 64; w++) bm = s_red[w] < bm ? s_red[w] : bm;
         if (bm != ND_NONE) atomicMin(&sc->kmin[qp], bm);
+        a.acnt[(qp ^ 1) * nb + blockIdx.x] = nkeep;
+        if (nkeep) atomicAdd(&sc->n_alive[qp ^ 1], nkeep);
       }
       if (!grid_barrier(&sc->barrier, nb, &sc->status)) break;
       const uint32_t nout = ld_acq32(&sc->n_alive[qp ^ 1]);
@@ -398,14 +489,14 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
       }
       const uint32_t kq = ld_acq32(&sc->kmin[qp]);
       if (gtid == 0) {
-        sc->n_alive[qp] = 0;         // becomes the output counter of the next scan
+        sc->n_alive[qp] = 0;         // becomes the total of the next scan
         sc->kmin[qp ^ 1] = ND_NONE;  // minimum of the next scan
       }
-      for (uint64_t base = blockIdx.x * (uint64_t)kPeelBlock; base < nout; base += nthreads) {
-        const uint64_t i = base + threadIdx.x;
+      for (uint32_t base = 0; base < nkeep; base += kPeelBlock) {
+        const uint32_t i = base + threadIdx.x;
         bool take = false;
         uint32_t id = 0;
-        if (i < nout) {
+        if (i < nkeep) {
           id = out[i];
           take = a.cnt[id] == kq;
         }
@@ -413,7 +504,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
         if (take) F[slot] = id;
       }
       scans++;
-      q++;
+      nscan++;
       k = kq;
       if (!grid_barrier(&sc->barrier, nb, &sc->status)) break;
       f = ld_acq32(&sc->fsize[t & 1]);
@@ -431,7 +522,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
         const uint32_t R = F[i];
         a.round[R] = t;
         a.cnt[R] = k;
-        w = Sh::work(g, R);
+        w = (Sh::len(g, R) + C - 1) / C;
       }
       // block-wide inclusive scan of w
       uint32_t incl = wave_incl_scan(w);
@@ -477,13 +568,10 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
     for (uint64_t base = blockIdx.x * (uint64_t)kPeelBlock + wv * 64ull; base < P;
          base += nthreads) {
       const uint64_t p = base + lane;
-      uint32_t others[NO];
-      bool push[NO];
-
-#pragma unroll
-      for (int j = 0; j < NO; j++) push[j] = false;
+      typename Sh::It it;
+      uint32_t R = 0, nprobe = 0;
       if (p < P) {
-        // block segment holding p, then the frontier slot inside it
+        // block segment holding unit p, then the frontier slot inside it
         uint32_t lo = 0, hi = nb;   // s_boff[lo] <= p < s_boff[hi]
         while (hi - lo > 1) {
           uint32_t mid = (lo + hi) >> 1;
@@ -499,10 +587,21 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
           if (a.wscan[mid] <= qoff) x0 = mid + 1;
           else x1 = mid;
         }
-        const uint32_t R = F[x0];
+        R = F[x0];
         const uint64_t before = (x0 > b0) ? a.wscan[x0 - 1] : 0;
-        const uint32_t idx = (uint32_t)(qoff - before);
-        if (Sh::visit(g, R, idx, others)) {
+        const uint32_t unit = (uint32_t)(qoff - before);
+        const uint32_t len = Sh::len(g, R);
+        const uint32_t i0 = unit * C;
+        nprobe = len - i0 < C ? len - i0 : C;
+        Sh::begin(g, R, i0, it);
+      }
+      uint32_t qroot = ND_NONE;   // cache key of R's set, formed on first use
+      for (uint32_t ci = 0; ci < C; ci++) {
+        uint32_t others[NO];
+        bool push[NO];
+#pragma unroll
+        for (int j = 0; j < NO; j++) push[j] = false;
+        if (ci < nprobe && Sh::step(g, it, others)) {
           visits++;
           uint32_t rr[NO];
           bool dead = false, lead = true;
@@ -522,24 +621,30 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
               }
             }
           }
-          uint32_t q = ND_NONE;
 #pragma unroll
           for (int j = 0; j < NO; j++) {
             if (rr[j] < t || (rr[j] == t && R < others[j])) {
-              if (q == ND_NONE) q = uf_find(a.uf, R);
-              const uint32_t x = uf_find(a.uf, others[j]);
-              if (x == q || lcache_hit(s_lcache, x, q)) continue;
+              if (qroot == ND_NONE) qroot = key_root(a.uf, R);
+              const uint32_t x = key_root(a.uf, others[j]);
+              if (x == qroot || lcache_hit(s_lcache, x, qroot)) continue;
+              const uint64_t key = ((uint64_t)x << 32) | qroot;
+              uint64_t *gslot = &a.gcache[gcache_slot(x, qroot, a.gcache_mask)];
+              if (*gslot == key) {
+                lcache_put(s_lcache, x, qroot);
+                continue;
+              }
               calls++;
               link_efficient(lc, others[j], R);
-              lcache_put(s_lcache, x, q);
+              lcache_put(s_lcache, x, qroot);
+              atomicExch((unsigned long long *)gslot, (unsigned long long)key);
             }
           }
         }
-      }
 #pragma unroll
-      for (int j = 0; j < NO; j++) {
-        uint32_t slot = wave_append(&sc->fsize[(t + 1) & 1], push[j]);
-        if (push[j]) Fn[slot] = others[j];
+        for (int j = 0; j < NO; j++) {
+          uint32_t slot = wave_append(&sc->fsize[(t + 1) & 1], push[j]);
+          if (push[j]) Fn[slot] = others[j];
+        }
       }
     }
     if (!grid_barrier(&sc->barrier, nb, &sc->status)) break;
@@ -631,10 +736,21 @@ nd_status nd_stage_peel(nd_ctx *c, const GraphView &g) {
   if (!(pa.al0 = (uint32_t *)nd_buf(c, B_AL0, nr * 4, &st))) return st;
   if (!(pa.al1 = (uint32_t *)nd_buf(c, B_AL1, nr * 4, &st))) return st;
   if (!(pa.btot = (uint64_t *)nd_buf(c, B_BTOT, (kMaxPeelBlocks + 1) * 8, &st))) return st;
+  if (!(pa.acnt = (uint32_t *)nd_buf(c, B_ACNT, 2 * kMaxPeelBlocks * 4, &st))) return st;
   pa.linkq_cap = 1u << 16;
   while (pa.linkq_cap < nr && pa.linkq_cap < (1u << 26)) pa.linkq_cap <<= 1;
   if (!(pa.linkq = (uint32_t *)nd_buf(c, B_LINKQ, pa.linkq_cap * 8ull, &st))) return st;
+  {
+    // 2^k entries, about one per 16 r-cliques, between 2^16 and 2^22
+    uint64_t ge = 1u << 16;
+    while (ge < (1u << 22) && ge * 16 < nr) ge <<= 1;
+    if (!(pa.gcache = (uint64_t *)nd_buf(c, B_GCACHE, ge * 8, &st))) return st;
+    pa.gcache_mask = ge - 1;
+    if ((st = nd_hip(c, hipMemsetAsync(pa.gcache, 0xFF, ge * 8, c->stream), "gcache")) != ND_OK)
+      return st;
+  }
   pa.sc = sc;
+  pa.chunk = c->work_chunk ? std::min<uint32_t>(c->work_chunk, 64) : 1;
   uint64_t wd = c->watchdog ? c->watchdog : nr + 2;
   pa.max_rounds = (uint32_t)std::min<uint64_t>(wd, 0xFFFFFFF0ull);
 
