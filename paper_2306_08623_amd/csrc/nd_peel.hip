@@ -38,7 +38,7 @@
 namespace {
 
 constexpr uint32_t kPeelBlock = 256;
-constexpr uint32_t kMaxPeelBlocks = 4096;
+constexpr uint32_t kMaxPeelBlocks = 2048;
 constexpr uint32_t kLocalStack = 8;
 constexpr uint32_t kLinkStepCap = 1u << 24;
 
@@ -61,7 +61,6 @@ struct PeelArgs {
   DevScalars *sc;
   uint32_t nblocks;
   uint32_t max_rounds;
-  uint32_t chunk;     // probe entries per lane task
 };
 
 // ---------------------------------------------------------------------------
@@ -206,27 +205,30 @@ __device__ void link_efficient(LinkCtx &c, uint32_t R0, uint32_t Q0) {
 // per-(r,s) s-clique discovery around a frontier r-clique
 // ---------------------------------------------------------------------------
 
-// First index >= x in the sorted range a[lo, hi) when the answer is known to
-// be >= lo: doubling steps from lo, then a binary search in the last step.
-// Consecutive probes of one chunk are ascending, so each search starts where
-// the previous one ended.
-__device__ __forceinline__ uint64_t gallop(const uint32_t *a, uint64_t lo, uint64_t hi,
-                                           uint32_t x) {
-  if (lo >= hi || a[lo] >= x) return lo;
-  uint64_t base = lo, step = 1;   // a[base] < x
-  while (base + step < hi && a[base + step] < x) {
+// First index x in [lo, hi) with a[x] > v for a non-decreasing array, when
+// the answer is known to be >= lo: doubling steps from lo, then a binary
+// search inside the last step.
+__device__ __forceinline__ uint64_t gallop_u64(const uint64_t *a, uint64_t lo, uint64_t hi,
+                                               uint64_t v) {
+  if (lo >= hi || a[lo] > v) return lo;
+  uint64_t base = lo, step = 1;   // a[base] <= v
+  while (base + step < hi && a[base + step] <= v) {
     base += step;
     step <<= 1;
   }
-  const uint64_t end = base + step + 1 < hi ? base + step + 1 : hi;
-  return lower_bound_u32<uint64_t>(a, base + 1, end, x);
+  uint64_t l = base + 1, h = base + step + 1 < hi ? base + step + 1 : hi;
+  while (l < h) {
+    const uint64_t mid = (l + h) >> 1;
+    if (a[mid] <= v) l = mid + 1;
+    else h = mid;
+  }
+  return l;
 }
 
-// Every shape lists, for a frontier r-clique R, its "probe" list (the
-// shortest adjacency-like list whose entries extend R to an s-clique
-// candidate). len() is its length; begin() positions an iterator at probe
-// index i0; step() tests the next probe entry and, when it closes an
-// s-clique, writes the ids of the other r-cliques of that s-clique.
+// Every shape lists, for a frontier r-clique R, its "probe" list: the
+// shortest adjacency-like list whose entries extend R to s-clique
+// candidates. len() is its length; visit() tests probe entry i and, when it
+// closes an s-clique, writes the ids of the other r-cliques of that s-clique.
 template <int R_, int S_>
 struct Shape;
 
@@ -234,17 +236,11 @@ struct Shape;
 template <>
 struct Shape<1, 2> {
   static constexpr int kOthers = 1;
-  struct It {
-    uint64_t sp;
-  };
   __device__ static uint32_t len(const GraphView &g, uint32_t R) {
     return (uint32_t)(g.rp[R + 1] - g.rp[R]);
   }
-  __device__ static void begin(const GraphView &g, uint32_t R, uint32_t i0, It &it) {
-    it.sp = g.rp[R] + i0;
-  }
-  __device__ static bool step(const GraphView &g, It &it, uint32_t *o) {
-    o[0] = g.col[it.sp++];
+  __device__ static bool visit(const GraphView &g, uint32_t R, uint32_t i, uint32_t *o) {
+    o[0] = g.col[g.rp[R] + i];
     return true;
   }
 };
@@ -254,28 +250,21 @@ struct Shape<1, 2> {
 template <>
 struct Shape<2, 3> {
   static constexpr int kOthers = 2;
-  struct It {
-    uint64_t sp, sq, eq;
-  };
   __device__ static uint32_t len(const GraphView &g, uint32_t R) {
     const uint32_t u = g.eu[R], v = g.ev[R];
     const uint64_t du = g.rp[u + 1] - g.rp[u], dv = g.rp[v + 1] - g.rp[v];
     return (uint32_t)(du < dv ? du : dv);
   }
-  __device__ static void begin(const GraphView &g, uint32_t R, uint32_t i0, It &it) {
+  __device__ static bool visit(const GraphView &g, uint32_t R, uint32_t i, uint32_t *o) {
     uint32_t p = g.eu[R], q = g.ev[R];
     if (g.rp[q + 1] - g.rp[q] < g.rp[p + 1] - g.rp[p]) { uint32_t t = p; p = q; q = t; }
-    it.sp = g.rp[p] + i0;
-    it.sq = g.rp[q];
-    it.eq = g.rp[q + 1];
-  }
-  __device__ static bool step(const GraphView &g, It &it, uint32_t *o) {
-    const uint64_t sp = it.sp++;
+    const uint64_t sp = g.rp[p] + i;
     const uint32_t x = g.col[sp];
-    it.sq = gallop(g.col, it.sq, it.eq, x);
-    if (it.sq == it.eq || g.col[it.sq] != x) return false;
+    const uint64_t bq = g.rp[q], eq = g.rp[q + 1];
+    const uint64_t sq = find_u32<uint64_t>(g.col, bq, eq, x);
+    if (sq == eq) return false;
     o[0] = g.eid[sp];
-    o[1] = g.eid[it.sq];
+    o[1] = g.eid[sq];
     return true;
   }
 };
@@ -286,9 +275,6 @@ struct Shape<2, 3> {
 template <>
 struct Shape<3, 4> {
   static constexpr int kOthers = 3;
-  struct It {
-    uint64_t p0, p1, f1, p2, f2;
-  };
   __device__ static uint32_t len(const GraphView &g, uint32_t R) {
     const uint32_t e0 = g.te[3ull * R], e1 = g.te[3ull * R + 1], e2 = g.te[3ull * R + 2];
     uint64_t s0 = g.wp[e0 + 1] - g.wp[e0], s1 = g.wp[e1 + 1] - g.wp[e1],
@@ -297,7 +283,7 @@ struct Shape<3, 4> {
     mn = mn < s2 ? mn : s2;
     return (uint32_t)mn;
   }
-  __device__ static void begin(const GraphView &g, uint32_t R, uint32_t i0, It &it) {
+  __device__ static bool visit(const GraphView &g, uint32_t R, uint32_t i, uint32_t *o) {
     uint32_t e0 = g.te[3ull * R], e1 = g.te[3ull * R + 1], e2 = g.te[3ull * R + 2];
     uint64_t s0 = g.wp[e0 + 1] - g.wp[e0], s1 = g.wp[e1 + 1] - g.wp[e1],
              s2 = g.wp[e2 + 1] - g.wp[e2];
@@ -307,22 +293,17 @@ struct Shape<3, 4> {
     } else if (s2 < s0 && s2 < s1) {
       uint32_t t = e0; e0 = e2; e2 = t;
     }
-    it.p0 = g.wp[e0] + i0;
-    it.p1 = g.wp[e1];
-    it.f1 = g.wp[e1 + 1];
-    it.p2 = g.wp[e2];
-    it.f2 = g.wp[e2 + 1];
-  }
-  __device__ static bool step(const GraphView &g, It &it, uint32_t *o) {
-    const uint64_t p0 = it.p0++;
+    const uint64_t p0 = g.wp[e0] + i;
     const uint32_t x = g.wc[p0];
-    it.p1 = gallop(g.wc, it.p1, it.f1, x);
-    if (it.p1 == it.f1 || g.wc[it.p1] != x) return false;
-    it.p2 = gallop(g.wc, it.p2, it.f2, x);
-    if (it.p2 == it.f2 || g.wc[it.p2] != x) return false;
+    const uint64_t b1 = g.wp[e1], f1 = g.wp[e1 + 1];
+    const uint64_t p1 = find_u32<uint64_t>(g.wc, b1, f1, x);
+    if (p1 == f1) return false;
+    const uint64_t b2 = g.wp[e2], f2 = g.wp[e2 + 1];
+    const uint64_t p2 = find_u32<uint64_t>(g.wc, b2, f2, x);
+    if (p2 == f2) return false;
     o[0] = g.wt[p0];
-    o[1] = g.wt[it.p1];
-    o[2] = g.wt[it.p2];
+    o[1] = g.wt[p1];
+    o[2] = g.wt[p2];
     return true;
   }
 };
@@ -338,7 +319,7 @@ struct Shape<3, 4> {
 // adds no information (its partner lies in x's set, which is connected to
 // q's set at x's level) and is skipped. Entries are single 64-bit LDS words,
 // so a lookup never sees half of an entry.
-constexpr uint32_t kLinkCache = 2048;
+constexpr uint32_t kLinkCache = 1024;
 
 __device__ __forceinline__ uint32_t lcache_slot(uint32_t x, uint32_t q) {
   return ((x * 0x9E3779B1u) ^ (q * 0x85EBCA77u) ^ (q >> 15)) & (kLinkCache - 1);
@@ -415,7 +396,6 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
   for (uint32_t i = threadIdx.x; i < kLinkCache; i += kPeelBlock) s_lcache[i] = ~0ull;
   __syncthreads();
 
-  const uint32_t C = a.chunk;   // probe entries per lane task
   uint32_t k = 0;
   uint32_t t = 0;
   uint32_t nscan = 0;   // bucket scans done
@@ -522,7 +502,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
         const uint32_t R = F[i];
         a.round[R] = t;
         a.cnt[R] = k;
-        w = (Sh::len(g, R) + C - 1) / C;
+        w = Sh::len(g, R);
       }
       // block-wide inclusive scan of w
       uint32_t incl = wave_incl_scan(w);
@@ -568,8 +548,10 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
     for (uint64_t base = blockIdx.x * (uint64_t)kPeelBlock + wv * 64ull; base < P;
          base += nthreads) {
       const uint64_t p = base + lane;
-      typename Sh::It it;
-      uint32_t R = 0, nprobe = 0;
+      uint32_t others[NO];
+      bool push[NO];
+#pragma unroll
+      for (int j = 0; j < NO; j++) push[j] = false;
       if (p < P) {
         // block segment holding unit p, then the frontier slot inside it
         uint32_t lo = 0, hi = nb;   // s_boff[lo] <= p < s_boff[hi]
@@ -581,27 +563,26 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
         const uint64_t qoff = p - s_boff[lo];
         const uint64_t b0 = min64((uint64_t)lo * seg, f);
         const uint64_t b1 = min64(b0 + seg, f);
-        uint64_t x0 = b0, x1 = b1;   // first slot with wscan > qoff
-        while (x0 < x1) {
-          uint64_t mid = (x0 + x1) >> 1;
-          if (a.wscan[mid] <= qoff) x0 = mid + 1;
-          else x1 = mid;
+        // first slot with wscan > qoff: lane 0 binary-searches its segment;
+        // the other lanes of the wave (consecutive units, mostly of the same
+        // r-clique) gallop forward from lane 0's slot when they share its
+        // segment
+        uint64_t x0 = b0;
+        if (lane == 0) {
+          uint64_t x1 = b1;
+          while (x0 < x1) {
+            uint64_t mid = (x0 + x1) >> 1;
+            if (a.wscan[mid] <= qoff) x0 = mid + 1;
+            else x1 = mid;
+          }
         }
-        R = F[x0];
+        const uint32_t lo_l0 = __shfl(lo, 0, 64);
+        const uint64_t x_l0 = __shfl(x0, 0, 64);
+        if (lane != 0) x0 = gallop_u64(a.wscan, lo == lo_l0 ? x_l0 : b0, b1, qoff);
+        const uint32_t R = F[x0];
         const uint64_t before = (x0 > b0) ? a.wscan[x0 - 1] : 0;
-        const uint32_t unit = (uint32_t)(qoff - before);
-        const uint32_t len = Sh::len(g, R);
-        const uint32_t i0 = unit * C;
-        nprobe = len - i0 < C ? len - i0 : C;
-        Sh::begin(g, R, i0, it);
-      }
-      uint32_t qroot = ND_NONE;   // cache key of R's set, formed on first use
-      for (uint32_t ci = 0; ci < C; ci++) {
-        uint32_t others[NO];
-        bool push[NO];
-#pragma unroll
-        for (int j = 0; j < NO; j++) push[j] = false;
-        if (ci < nprobe && Sh::step(g, it, others)) {
+        const uint32_t idx = (uint32_t)(qoff - before);
+        if (Sh::visit(g, R, idx, others)) {
           visits++;
           uint32_t rr[NO];
           bool dead = false, lead = true;
@@ -621,6 +602,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
               }
             }
           }
+          uint32_t qroot = ND_NONE;   // cache key of R's set, formed on first use
 #pragma unroll
           for (int j = 0; j < NO; j++) {
             if (rr[j] < t || (rr[j] == t && R < others[j])) {
@@ -640,11 +622,11 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
             }
           }
         }
+      }
 #pragma unroll
-        for (int j = 0; j < NO; j++) {
-          uint32_t slot = wave_append(&sc->fsize[(t + 1) & 1], push[j]);
-          if (push[j]) Fn[slot] = others[j];
-        }
+      for (int j = 0; j < NO; j++) {
+        uint32_t slot = wave_append(&sc->fsize[(t + 1) & 1], push[j]);
+        if (push[j]) Fn[slot] = others[j];
       }
     }
     if (!grid_barrier(&sc->barrier, nb, &sc->status)) break;
@@ -750,7 +732,6 @@ nd_status nd_stage_peel(nd_ctx *c, const GraphView &g) {
       return st;
   }
   pa.sc = sc;
-  pa.chunk = c->work_chunk ? std::min<uint32_t>(c->work_chunk, 64) : 1;
   uint64_t wd = c->watchdog ? c->watchdog : nr + 2;
   pa.max_rounds = (uint32_t)std::min<uint64_t>(wd, 0xFFFFFFF0ull);
 
