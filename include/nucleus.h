@@ -143,6 +143,14 @@ nd_status nd_get_counts(nd_ctx *ctx, uint32_t *out, nd_mem where);
 /* Core numbers: uint32[n_r], indexed by r-clique index. */
 nd_status nd_get_coreness(nd_ctx *ctx, uint32_t *out, nd_mem where);
 
+/* Peel round of every r-clique: uint32[n_r]. Rounds are numbered from 0;
+ * all r-cliques peeled in one round share a core number, and core numbers
+ * never decrease from one round to the next (Algorithm 3's loop). With the
+ * counts this certifies the core numbers: for every r-clique R, at least
+ * ND[R] s-cliques containing R have all members of core >= ND[R], and at
+ * most ND[R] have all members peeled in R's round or later. */
+nd_status nd_get_peel_rounds(nd_ctx *ctx, uint32_t *out, nd_mem where);
+
 /* Canonical tree: parent uint64[n_r + n_int] (UINT64_MAX for roots) and
  * level uint32[n_int] (level of node n_r + i). Either pointer may be NULL. */
 nd_status nd_get_tree(nd_ctx *ctx, uint64_t *parent, uint32_t *level, nd_mem where);

@@ -10,6 +10,7 @@ import ctypes as C
 import os
 import subprocess
 from dataclasses import dataclass
+from math import comb
 
 import numpy as np
 
@@ -70,6 +71,17 @@ def _load():
         lib.ndo_count.restype = C.c_int
         lib.ndo_free.argtypes = [C.POINTER(_Result)]
         lib.ndo_free.restype = None
+        lib.ndo_open.argtypes = [C.c_uint32, u64p, u32p, C.c_uint32, C.c_uint32,
+                                 C.POINTER(C.c_void_p)]
+        lib.ndo_open.restype = C.c_int
+        lib.ndo_graph_n_r.argtypes = [C.c_void_p]
+        lib.ndo_graph_n_r.restype = C.c_uint64
+        lib.ndo_graph_rcliques.argtypes = [C.c_void_p, u32p]
+        lib.ndo_graph_rcliques.restype = None
+        lib.ndo_incident.argtypes = [C.c_void_p, C.c_uint64, u64p, C.c_uint64]
+        lib.ndo_incident.restype = C.c_uint64
+        lib.ndo_close.argtypes = [C.c_void_p]
+        lib.ndo_close.restype = None
         _lib = lib
     return _lib
 
@@ -150,6 +162,48 @@ def _run(fn_name: str, csr, r: int, s: int, full: bool) -> Decomposition:
         return d
     finally:
         lib.ndo_free(C.byref(res))
+
+
+class Graph:
+    """Per-r-clique queries (the oracle's own listing and s-clique scan) for
+    graphs too large for a full decomposition."""
+
+    def __init__(self, csr, r: int, s: int):
+        lib = _load()
+        rp, col = _csr_args(csr)
+        self._keep = (rp, col)
+        h = C.c_void_p()
+        st = lib.ndo_open(csr.n, rp.ctypes.data_as(C.POINTER(C.c_uint64)),
+                          col.ctypes.data_as(C.POINTER(C.c_uint32)), r, s, C.byref(h))
+        if st != NDO_OK:
+            raise OracleError(st)
+        self.h = h
+        self.r, self.s = r, s
+        self.n_r = int(lib.ndo_graph_n_r(h))
+        self.others_per_s = comb(s, r) - 1
+
+    def rcliques(self) -> np.ndarray:
+        out = np.zeros((self.n_r, self.r), dtype=np.uint32)
+        if self.n_r:
+            _load().ndo_graph_rcliques(self.h, out.ctypes.data_as(C.POINTER(C.c_uint32)))
+        return out
+
+    def incident(self, rid: int) -> np.ndarray:
+        """[n_S, C(s,r)-1] ids of the other r-cliques of every s-clique
+        containing r-clique ``rid``."""
+        lib = _load()
+        n_s = int(lib.ndo_incident(self.h, rid, None, 0))
+        out = np.zeros(max(1, n_s * self.others_per_s), dtype=np.uint64)
+        lib.ndo_incident(self.h, rid, out.ctypes.data_as(C.POINTER(C.c_uint64)), out.size)
+        return out[: n_s * self.others_per_s].reshape(n_s, self.others_per_s)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _load().ndo_close(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
 
 
 def decompose(csr, r: int, s: int) -> Decomposition:

@@ -722,3 +722,84 @@ int ndo_decompose(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
   free(T.first);
   return NDO_OK;
 }
+
+/* ---- per-r-clique queries -------------------------------------------------- */
+
+struct ndo_graph {
+  graph g;
+  rtable T;
+  uint32_t r, s;
+  subsets sb;
+  sscan X;
+  uint64_t self, nS, cap, nout;
+  uint64_t *out;
+};
+
+static void emit_incident(const uint32_t *S, void *ctx) {
+  struct ndo_graph *G = (struct ndo_graph *)ctx;
+  uint32_t sub[MAXS];
+  G->nS++;
+  for (uint32_t i = 0; i < G->sb.nm; i++) {
+    subset_tuple(S, G->s, G->sb.mask[i], sub);
+    uint64_t id = rlookup(&G->T, sub);
+    if (id == G->self) continue;
+    if (G->nout < G->cap) G->out[G->nout] = id;
+    G->nout++;
+  }
+}
+
+int ndo_open(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, uint32_t r, uint32_t s,
+             ndo_graph **out) {
+  if (!out) return NDO_E_INVALID_ARG;
+  *out = NULL;
+  if (r < 1 || s <= r || s > MAXS) return NDO_E_INVALID_ARG;
+  struct ndo_graph *G = (struct ndo_graph *)calloc(1, sizeof(*G));
+  if (!G) return NDO_E_OOM;
+  int st = build_graph(&G->g, n, row_ptr, col);
+  if (st != NDO_OK) { free(G); return st; }
+  G->r = r;
+  G->s = s;
+  rcollect rc;
+  memset(&rc, 0, sizeof(rc));
+  rc.r = r;
+  st = list_cliques(&G->g, r, emit_rcollect, &rc);
+  if (st != NDO_OK || rc.v.oom) { free(rc.v.a); free(G); return NDO_E_OOM; }
+  G->T.r = r;
+  G->T.n_r = rc.v.n / r;
+  G->T.t = rc.v.a ? rc.v.a : (uint32_t *)malloc(sizeof(uint32_t));
+  G->T.first = (uint64_t *)calloc((uint64_t)n + 1, sizeof(uint64_t));
+  if (!G->T.t || !G->T.first) { ndo_close(G); return NDO_E_OOM; }
+  for (uint64_t i = 0; i < G->T.n_r; i++) G->T.first[G->T.t[i * r] + 1]++;
+  for (uint32_t a = 0; a < n; a++) G->T.first[a + 1] += G->T.first[a];
+  make_subsets(&G->sb, r, s);
+  if (sscan_init(&G->X, &G->g, r, s, emit_incident, G) != NDO_OK) { ndo_close(G); return NDO_E_OOM; }
+  *out = G;
+  return NDO_OK;
+}
+
+uint64_t ndo_graph_n_r(const ndo_graph *G) { return G ? G->T.n_r : 0; }
+
+void ndo_graph_rcliques(const ndo_graph *G, uint32_t *out) {
+  if (G && out && G->T.n_r) memcpy(out, G->T.t, G->T.n_r * G->r * sizeof(uint32_t));
+}
+
+uint64_t ndo_incident(ndo_graph *G, uint64_t id, uint64_t *out, uint64_t cap) {
+  if (!G || id >= G->T.n_r) return 0;
+  uint32_t tup[MAXS];
+  memcpy(tup, G->T.t + id * G->r, G->r * sizeof(uint32_t));
+  G->self = id;
+  G->nS = 0;
+  G->nout = 0;
+  G->out = out;
+  G->cap = out ? cap : 0;
+  for_each_sclique(&G->X, tup);
+  return G->nS;
+}
+
+void ndo_close(ndo_graph *G) {
+  if (!G) return;
+  sscan_free(&G->X);
+  free(G->T.t);
+  free(G->T.first);
+  free(G);
+}

@@ -82,6 +82,22 @@ int ndo_count(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
 
 void ndo_free(ndo_result *res);
 
+/* Per-r-clique queries on a graph too large for a full decomposition.
+ * ndo_open lists the r-cliques (O1) once; ndo_incident then enumerates the
+ * s-cliques containing one r-clique. */
+typedef struct ndo_graph ndo_graph;
+
+int ndo_open(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, uint32_t r, uint32_t s,
+             ndo_graph **out);
+uint64_t ndo_graph_n_r(const ndo_graph *G);
+/* copies the n_r * r lexicographic r-clique tuples */
+void ndo_graph_rcliques(const ndo_graph *G, uint32_t *out);
+/* For r-clique `id`: the number of s-cliques containing it. If cap is large
+ * enough, out receives, for each such s-clique in listing order, the ids of
+ * its other C(s,r)-1 r-cliques (cap counts uint64 slots). */
+uint64_t ndo_incident(ndo_graph *G, uint64_t id, uint64_t *out, uint64_t cap);
+void ndo_close(ndo_graph *G);
+
 #ifdef __cplusplus
 }
 #endif

@@ -349,6 +349,14 @@ nd_status nd_get_coreness(nd_ctx *c, uint32_t *out, nd_mem where) {
   return copy_out(c, out, c->bufs[B_CNT].p, c->n_r * 4ull, where);
 }
 
+nd_status nd_get_peel_rounds(nd_ctx *c, uint32_t *out, nd_mem where) {
+  if (!c || (!out && c->n_r)) return ND_E_INVALID_ARG;
+  nd_status st = set_dev(c);
+  if (st != ND_OK) return st;
+  if (!c->decomposed) return nd_fail(c, ND_E_STATE, "no decomposition result");
+  return copy_out(c, out, c->bufs[B_ROUND].p, c->n_r * 4ull, where);
+}
+
 nd_status nd_get_tree(nd_ctx *c, uint64_t *parent, uint32_t *level, nd_mem where) {
   if (!c) return ND_E_INVALID_ARG;
   nd_status st = set_dev(c);

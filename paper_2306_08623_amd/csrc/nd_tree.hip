@@ -248,7 +248,8 @@ nd_status nd_stage_tree(nd_ctx *c, const GraphView &g) {
   uint32_t *sz = (uint32_t *)c->bufs[B_F1].p;
   uint32_t *npar = (uint32_t *)c->bufs[B_AL0].p;
   uint32_t *nkid = (uint32_t *)c->bufs[B_AL1].p;
-  uint32_t *ml = (uint32_t *)c->bufs[B_ROUND].p;    // peel rounds are no longer needed
+  uint32_t *ml = (uint32_t *)nd_buf(c, B_TMP32A, nr * 4, &st);   // min leaf per node
+  if (!ml) return st;
   uint64_t *pos = (uint64_t *)c->bufs[B_WSCAN].p;   // n_r + 1 needed
   uint32_t *flag = (uint32_t *)nd_buf(c, B_TMP32D, nr * 4, &st);
   if (!flag) return st;

@@ -43,7 +43,8 @@ NONE64 = np.uint64(0xFFFFFFFFFFFFFFFF)
 # Every function the C ABI exports (kept in sync with include/nucleus.h).
 EXPORTS = [
     "nd_create", "nd_destroy", "nd_load_csr", "nd_set_rs", "nd_decompose", "nd_sync",
-    "nd_get_info", "nd_get_rcliques", "nd_get_counts", "nd_get_coreness", "nd_get_tree",
+    "nd_get_info", "nd_get_rcliques", "nd_get_counts", "nd_get_coreness", "nd_get_peel_rounds",
+    "nd_get_tree",
     "nd_status_str", "nd_last_error",
 ]
 
@@ -126,7 +127,7 @@ def load_library(path: str = LIB_PATH):
     lib.nd_sync.restype = C.c_int
     lib.nd_get_info.argtypes = [vp, C.POINTER(Info)]
     lib.nd_get_info.restype = C.c_int
-    for name in ("nd_get_rcliques", "nd_get_counts", "nd_get_coreness"):
+    for name in ("nd_get_rcliques", "nd_get_counts", "nd_get_coreness", "nd_get_peel_rounds"):
         getattr(lib, name).argtypes = [vp, vp, C.c_int]
         getattr(lib, name).restype = C.c_int
     lib.nd_get_tree.argtypes = [vp, vp, vp, C.c_int]
@@ -273,6 +274,13 @@ class Context:
             out = np.zeros(n_r, dtype=np.uint32)
         p, kind = _ptr(out)
         self._check(self.lib.nd_get_coreness(self.h, p if n_r else None, kind))
+        return out
+
+    def nd_get_peel_rounds(self) -> np.ndarray:
+        n_r = self.nd_get_info()["n_r"]
+        out = np.zeros(n_r, dtype=np.uint32)
+        self._check(self.lib.nd_get_peel_rounds(self.h, out.ctypes.data if out.size else None,
+                                                ND_MEM_HOST))
         return out
 
     def nd_get_tree(self) -> tuple[np.ndarray, np.ndarray]:

@@ -1,0 +1,113 @@
+"""Full-size parity on the R-MAT scale-18 workload (262,144 vertices, edge
+factor 16, seed 2), in the launch configuration the benchmark times.
+
+* (1,2): the whole oracle runs live (seconds); element-by-element compare.
+* (2,3): the oracle's full results were hashed once by
+  tests/golden/make_golden.py (about 9 minutes on one core); the GPU outputs
+  must hash identically.
+* (3,4): a full oracle run would take hours. The r-clique listing is compared
+  in full against the oracle's own listing; counts and core numbers are
+  checked on 20,000 sampled triangles against values the oracle computes one
+  triangle at a time, with the certificates of tests/certify.py; the tree is
+  checked for the properties that hold at any size, for adjacency closure on
+  sampled triangles and for connectivity of sampled small nodes.
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+from math import comb
+
+import numpy as np
+import pytest
+
+import certify
+import oracle
+from paper_2306_08623_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "golden"))
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def rmat18():
+    return I.workload_rmat18()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2306_08623_amd import nucleus
+    c = nucleus.Context(device=0)
+    yield c
+    c.close()
+
+
+@pytest.mark.timeout(300)
+def test_rmat18_12_full(ctx, rmat18):
+    _say("[fullsize] rmat18 (1,2) vs the full oracle")
+    res = ctx.decompose(rmat18, 1, 2)
+    d = oracle.decompose(rmat18, 1, 2)
+    assert np.array_equal(res.counts.astype(np.uint64), d.count)
+    assert np.array_equal(res.coreness.astype(np.uint64), d.coreness)
+    assert np.array_equal(res.parent, d.parent)
+    assert np.array_equal(res.level.astype(np.uint64), d.level)
+
+
+@pytest.mark.timeout(300)
+def test_rmat18_23_golden(ctx, rmat18):
+    from make_golden import result_hashes
+    with open(os.path.join(HERE, "golden", "rmat18_23.json")) as f:
+        gold = json.load(f)
+    assert gold["csr_sha256"] == rmat18.sha256()
+    _say("[fullsize] rmat18 (2,3) vs the oracle's hashed results")
+    res = ctx.decompose(rmat18, 2, 3)
+    info = res.info
+    assert (info["n_r"], info["n_s"], info["k"], info["n_int"]) == \
+        (gold["n_r"], gold["n_s"], gold["k"], gold["n_int"])
+    got = result_hashes(res.rcliques, res.counts, res.coreness, res.parent, res.level)
+    assert got == gold["sha256"]
+
+
+@pytest.mark.timeout(900)
+def test_rmat18_34_sampled(ctx, rmat18):
+    _say("[fullsize] rmat18 (3,4): GPU decomposition")
+    ctx.load_csr(rmat18)
+    ctx.nd_set_rs(3, 4)
+    ctx.nd_decompose()
+    info = ctx.nd_get_info()
+    rcl = ctx.nd_get_rcliques()
+    counts = ctx.nd_get_counts()
+    core = ctx.nd_get_coreness()
+    rounds = ctx.nd_get_peel_rounds()
+    parent, level = ctx.nd_get_tree()
+    n_r = info["n_r"]
+    # every 4-clique has 4 triangles; every (triangle, 4-clique) pair visited once
+    assert int(counts.astype(np.uint64).sum()) == comb(4, 3) * info["n_s"]
+    assert info["visits"] == comb(4, 3) * info["n_s"]
+    assert int(core.max()) == info["k"]
+    assert np.all(core <= counts)
+    _say("[fullsize] rmat18 (3,4): oracle triangle listing")
+    G = oracle.Graph(rmat18, 3, 4)
+    assert G.n_r == n_r
+    assert np.array_equal(G.rcliques(), rcl)
+    rng = np.random.default_rng(34)
+    sample = rng.choice(n_r, size=min(n_r, 20000), replace=False)
+    # always include the extremes
+    sample = np.unique(np.concatenate([sample, [int(np.argmax(core)), int(np.argmax(counts)),
+                                                int(np.argmin(core))]]))
+    _say(f"[fullsize] rmat18 (3,4): certificates on {sample.size} triangles")
+    certify.check_core_certificates(G, core, rounds, counts, sample)
+    _say("[fullsize] rmat18 (3,4): tree properties")
+    certify.check_tree_properties(parent, level, core, n_r)
+    npairs = certify.check_adjacency_closure(G, parent, level, core, n_r, sample[:3000])
+    assert npairs > 0
+    nodes = certify.check_small_nodes_connected(G, parent, level, core, n_r)
+    _say(f"[fullsize] rmat18 (3,4): {npairs} adjacent pairs closed, {nodes} small nodes connected")
+    G.close()
