@@ -116,9 +116,9 @@ void nd_destroy(nd_ctx *ctx);
 nd_status nd_load_csr(nd_ctx *ctx, uint32_t n, uint64_t nnz, const uint64_t *row_ptr,
                       const uint32_t *col, nd_mem where);
 
-/* Choose (r,s): supported pairs are (1,2), (2,3), (3,4), (1,3), (2,4), (1,4).
- * Other 1 <= r < s pairs return ND_E_UNSUPPORTED; r >= s returns
- * ND_E_INVALID_ARG. */
+/* Choose (r,s): supported pairs are (1,2) (k-core), (2,3) (k-truss) and
+ * (3,4). Other 1 <= r < s pairs return ND_E_UNSUPPORTED; r < 1 or r >= s
+ * returns ND_E_INVALID_ARG. */
 nd_status nd_set_rs(nd_ctx *ctx, uint32_t r, uint32_t s);
 
 /* Run the whole pipeline on the context's stream: orientation, r-clique
@@ -154,6 +154,52 @@ nd_status nd_get_peel_rounds(nd_ctx *ctx, uint32_t *out, nd_mem where);
 /* Canonical tree: parent uint64[n_r + n_int] (UINT64_MAX for roots) and
  * level uint32[n_int] (level of node n_r + i). Either pointer may be NULL. */
 nd_status nd_get_tree(nd_ctx *ctx, uint64_t *parent, uint32_t *level, nd_mem where);
+
+/* ---- Batches of independent graphs ------------------------------------
+ *
+ * One call decomposes many graphs. Graphs sharing (r,s) run together as one
+ * disjoint union: the decomposition of a union is the union of the
+ * decompositions (no s-clique spans two graphs, so counts, core numbers and
+ * hierarchy components are each those of one graph; Section 3 definitions),
+ * so each (r,s) group costs one pipeline with one persistent peel launch.
+ * Every graph's results are exactly those of decomposing it alone. */
+
+typedef struct nd_graph_desc {
+  uint32_t n;                /* vertices                                         */
+  uint32_t r, s;             /* (r,s) of this graph                              */
+  uint64_t nnz;              /* entries of col (2m)                              */
+  const uint64_t *row_ptr;   /* uint64[n+1], same rules as nd_load_csr           */
+  const uint32_t *col;       /* uint32[nnz]                                      */
+} nd_graph_desc;
+
+typedef struct nd_graph_result {
+  nd_status status;          /* ND_OK, or the error of this graph's group        */
+  uint32_t k;                /* max core number (0 if no r-clique)               */
+  uint64_t n_r;              /* r-cliques                                        */
+  uint64_t n_s;              /* s-cliques                                        */
+  uint64_t n_int;            /* internal nodes of the canonical tree             */
+} nd_graph_result;
+
+/* Decompose graphs[0..G) (all host or all device pointers, per `where`; the
+ * caller keeps ownership and may free them when the call returns). Fills
+ * results[0..G). Validation (when on) checks every graph: a graph whose
+ * row_ptr does not run from 0 to nnz, or whose columns leave 0..n-1, fails
+ * its group with ND_E_BAD_GRAPH. Supported (r,s) as for nd_set_rs. The sum of
+ * n over one (r,s) group must stay below 2^32-1, and so must its edges.
+ * Results stay on the device until the next nd_batch_decompose; the call
+ * replaces the context's loaded graph (load again before nd_decompose).
+ * nd_get_info afterwards reports totals over the batch (r = s = 0 when the
+ * batch mixes pairs). On error the batch results are released. */
+nd_status nd_batch_decompose(nd_ctx *ctx, uint32_t G, const nd_graph_desc *graphs, nd_mem where,
+                             nd_graph_result *results);
+
+/* Results of graph i of the last batch, in that graph's own numbering (its
+ * vertices 0..n-1, its r-cliques 0..n_r-1 in lexicographic order, its tree
+ * nodes n_r..n_r+n_int-1 in canonical order): identical to nd_get_rcliques /
+ * nd_get_counts / nd_get_coreness / nd_get_tree after decomposing graph i
+ * alone. Sizes come from results[i]; any pointer may be NULL. */
+nd_status nd_batch_get(nd_ctx *ctx, uint32_t i, uint32_t *rcliques, uint32_t *counts,
+                       uint32_t *coreness, uint64_t *parent, uint32_t *level, nd_mem where);
 
 const char *nd_status_str(nd_status st);
 

@@ -22,7 +22,7 @@ nd_status nd_hip(nd_ctx *c, hipError_t e, const char *what) {
 
 void *nd_buf(nd_ctx *c, int id, size_t bytes, nd_status *st) {
   *st = ND_OK;
-  if ((int)c->bufs.size() < B_COUNT) c->bufs.resize(B_COUNT);
+  if ((int)c->bufs.size() <= id) c->bufs.resize(std::max(id + 1, (int)B_COUNT));
   DevBuf &b = c->bufs[id];
   if (bytes == 0) bytes = 8;
   if (b.p && b.bytes >= bytes) return b.p;
@@ -151,6 +151,7 @@ void nd_destroy(nd_ctx *c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  nd_batch_release(c);
   for (auto &b : c->bufs)
     if (b.p) (void)hipFree(b.p);
   for (int i = 0; i < 10; i++)
@@ -165,6 +166,7 @@ nd_status nd_load_csr(nd_ctx *c, uint32_t n, uint64_t nnz, const uint64_t *row_p
   if (st != ND_OK) return st;
   c->have_graph = false;
   c->decomposed = false;
+  c->info_valid = false;
   if (!row_ptr || (nnz && !col)) return nd_fail(c, ND_E_INVALID_ARG, "NULL row_ptr or col");
   if (where != ND_MEM_HOST && where != ND_MEM_DEVICE)
     return nd_fail(c, ND_E_INVALID_ARG, "bad memory kind");
@@ -207,6 +209,7 @@ nd_status nd_set_rs(nd_ctx *c, uint32_t r, uint32_t s) {
   c->r = r;
   c->s = s;
   c->decomposed = false;
+  c->info_valid = false;
   return ND_OK;
 }
 
@@ -228,14 +231,13 @@ static nd_status check_device_status(nd_ctx *c, DevScalars *host) {
   return ND_OK;
 }
 
-nd_status nd_decompose(nd_ctx *c) {
-  if (!c) return ND_E_INVALID_ARG;
-  nd_status st = set_dev(c);
-  if (st != ND_OK) return st;
-  if (!c->have_graph) return nd_fail(c, ND_E_STATE, "no graph loaded");
-  if (!c->r) return nd_fail(c, ND_E_STATE, "r and s not set");
+}  // extern "C"
+
+// The whole pipeline on the graph held in B_RP / B_COL (n, nnz, r, s set).
+nd_status nd_run_pipeline(nd_ctx *c) {
+  nd_status st;
   c->decomposed = false;
-  c->last_error.clear();
+  c->info_valid = false;
   memset(&c->info, 0, sizeof(c->info));
   DevScalars *sc = (DevScalars *)c->bufs[B_SCAL].p;
   if ((st = nd_hip(c, hipMemsetAsync(sc, 0, sizeof(DevScalars), c->stream), "scalars")) != ND_OK)
@@ -288,7 +290,20 @@ nd_status nd_decompose(nd_ctx *c) {
     (void)hipGetLastError();
   }
   c->decomposed = true;
+  c->info_valid = true;
   return ND_OK;
+}
+
+extern "C" {
+
+nd_status nd_decompose(nd_ctx *c) {
+  if (!c) return ND_E_INVALID_ARG;
+  nd_status st = set_dev(c);
+  if (st != ND_OK) return st;
+  if (!c->have_graph) return nd_fail(c, ND_E_STATE, "no graph loaded");
+  if (!c->r) return nd_fail(c, ND_E_STATE, "r and s not set");
+  c->last_error.clear();
+  return nd_run_pipeline(c);
 }
 
 nd_status nd_sync(nd_ctx *c) {
@@ -301,7 +316,7 @@ nd_status nd_sync(nd_ctx *c) {
 
 nd_status nd_get_info(nd_ctx *c, nd_info *out) {
   if (!c || !out) return ND_E_INVALID_ARG;
-  if (!c->decomposed) return nd_fail(c, ND_E_STATE, "no decomposition result");
+  if (!c->info_valid) return nd_fail(c, ND_E_STATE, "no decomposition result");
   *out = c->info;
   return ND_OK;
 }

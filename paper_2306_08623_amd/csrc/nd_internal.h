@@ -199,6 +199,10 @@ struct nd_ctx {
   uint64_t nnz = 0, m = 0;
   uint32_t r = 0, s = 0;
   bool decomposed = false;
+  bool info_valid = false;   // info holds the last decomposition or batch
+
+  // results of the last nd_batch_decompose (nd_batch.hip)
+  struct BatchState *batch = nullptr;
 
   // named device buffers (grow-only)
   std::vector<DevBuf> bufs;
@@ -227,9 +231,15 @@ enum BufId : int {
   B_F0, B_F1, B_WSCAN, B_AL0, B_AL1, B_BTOT, B_LINKQ,
   B_SCAL, B_TMP64, B_TMP32A, B_TMP32B, B_TMP32C, B_TMP32D,
   B_SORTK0, B_SORTK1, B_SORTV0, B_SORTV1, B_HIST,
-  B_PARENT, B_LEVEL, B_RCL, B_GCACHE, B_ACNT,
+  B_PARENT, B_LEVEL, B_RCL, B_GCACHE, B_ACNT, B_NODEML, B_SORTOFF,
+  B_BATCHDESC,
   B_COUNT
 };
+
+// batch arena: per (r,s) group, kBatchFields grow-only slots after B_COUNT
+constexpr int kBatchFields = 10;
+constexpr int kBatchGroups = 3;
+inline int nd_batch_slot(int group, int field) { return B_COUNT + group * kBatchFields + field; }
 
 // device scalars block (one per context)
 struct DevScalars {
@@ -256,12 +266,21 @@ nd_status nd_fail(nd_ctx *c, nd_status st, const std::string &msg);
 void *nd_buf(nd_ctx *c, int id, size_t bytes, nd_status *st);
 nd_status nd_hip(nd_ctx *c, hipError_t e, const char *what);
 
+// releases the host state of the last batch (nd_batch.hip)
+void nd_batch_release(nd_ctx *c);
+
+// the whole decomposition of the graph held in the context (nd_api.hip)
+nd_status nd_run_pipeline(nd_ctx *c);
+nd_status nd_validate_loaded(nd_ctx *c);
+
 // pipeline stages (each returns ND_OK or an error already recorded in ctx)
 nd_status nd_stage_prep(nd_ctx *c, GraphView *gv);
 nd_status nd_stage_count(nd_ctx *c, const GraphView &gv);
 nd_status nd_stage_peel(nd_ctx *c, const GraphView &gv);
 nd_status nd_stage_tree(nd_ctx *c, const GraphView &gv);
 nd_status nd_write_rcliques(nd_ctx *c, const GraphView &gv, uint32_t *out_dev);
+nd_status nd_sort_pairs_u64(nd_ctx *c, uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1,
+                            uint64_t n, uint32_t bits, uint64_t **out_k, uint32_t **out_v);
 
 // small device utilities (nd_prep.hip)
 nd_status nd_exclusive_scan_u64(nd_ctx *c, const uint64_t *in_dev, uint64_t *out_dev, uint64_t n,

@@ -201,10 +201,13 @@ __global__ void k_write_tree(uint64_t n_r, uint64_t n_int, const uint32_t *__res
 }
 
 __global__ void k_canon(uint64_t n_int, const uint32_t *__restrict__ sorted_val,
-                        uint32_t *__restrict__ canon) {
+                        const uint32_t *__restrict__ ml, uint32_t *__restrict__ canon,
+                        uint32_t *__restrict__ node_ml) {
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n_int;
-       i += (uint64_t)gridDim.x * blockDim.x)
+       i += (uint64_t)gridDim.x * blockDim.x) {
     canon[sorted_val[i]] = (uint32_t)i;
+    node_ml[i] = ml[sorted_val[i]];
+  }
 }
 
 __global__ void k_rcliques(uint32_t r, uint64_t n_r, const uint32_t *__restrict__ eu,
@@ -233,6 +236,34 @@ uint32_t bits_for(uint64_t v) {
 }
 
 }  // namespace
+
+// Stable LSD radix sort of n (u64 key, u32 value) pairs on the context's
+// stream, `bits` low key bits significant; k1/v1 are scratch of the same
+// size. *out_k / *out_v point at whichever buffers hold the result.
+nd_status nd_sort_pairs_u64(nd_ctx *c, uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1,
+                            uint64_t n, uint32_t bits, uint64_t **out_k, uint32_t **out_v) {
+  nd_status st = ND_OK;
+  if (n) {
+    const uint32_t ntiles = (uint32_t)((n + kSortTile - 1) / kSortTile);
+    uint32_t *hist = (uint32_t *)nd_buf(c, B_HIST, 256ull * ntiles * 4, &st);
+    if (!hist) return st;
+    uint64_t *hoff = (uint64_t *)nd_buf(c, B_SORTOFF, (256ull * ntiles + 1) * 8, &st);
+    if (!hoff) return st;
+    for (uint32_t shift = 0; shift < bits; shift += 8) {
+      hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kTB), 0, c->stream, k0, n, shift,
+                         ntiles, hist);
+      st = nd_exclusive_scan_u32_to_u64(c, hist, hoff, 256ull * ntiles, nullptr);
+      if (st != ND_OK) return st;
+      hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(kTB), 0, c->stream, k0, v0, n,
+                         shift, ntiles, hoff, k1, v1);
+      std::swap(k0, k1);
+      std::swap(v0, v1);
+    }
+  }
+  *out_k = k0;
+  *out_v = v0;
+  return nd_hip(c, hipGetLastError(), "radix sort");
+}
 
 nd_status nd_stage_tree(nd_ctx *c, const GraphView &g) {
   (void)g;
@@ -291,25 +322,15 @@ nd_status nd_stage_tree(nd_ctx *c, const GraphView &g) {
     hipLaunchKernelGGL(k_kept_keys, dim3(grid), dim3(kTB), 0, c->stream, nr, flag, pos, nd, ml,
                        lbits, k0, v0);
     // key bits: level < 2^32, min leaf < 2^lbits
-    const uint32_t kbits = lbits + 32;
-    const uint32_t ntiles = (uint32_t)((nint + kSortTile - 1) / kSortTile);
-    uint32_t *hist = (uint32_t *)nd_buf(c, B_HIST, 256ull * ntiles * 4, &st);
-    if (!hist) return st;
-    uint64_t *hoff = (uint64_t *)nd_buf(c, B_RCL, (256ull * ntiles + 1) * 8, &st);
-    if (!hoff) return st;
-    for (uint32_t shift = 0; shift < kbits; shift += 8) {
-      hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(kTB), 0, c->stream, k0, nint, shift,
-                         ntiles, hist);
-      st = nd_exclusive_scan_u32_to_u64(c, hist, hoff, 256ull * ntiles, nullptr);
-      if (st != ND_OK) return st;
-      hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(kTB), 0, c->stream, k0, v0, nint,
-                         shift, ntiles, hoff, k1, v1);
-      std::swap(k0, k1);
-      std::swap(v0, v1);
-    }
-    sorted_val = v0;
+    uint64_t *ks = nullptr;
+    uint32_t *vs = nullptr;
+    st = nd_sort_pairs_u64(c, k0, v0, k1, v1, nint, lbits + 32, &ks, &vs);
+    if (st != ND_OK) return st;
+    sorted_val = vs;
+    uint32_t *node_ml = (uint32_t *)nd_buf(c, B_NODEML, nint * 4, &st);
+    if (!node_ml) return st;
     hipLaunchKernelGGL(k_canon, dim3(nd_grid(nint, kTB, 16384)), dim3(kTB), 0, c->stream, nint,
-                       sorted_val, canon);
+                       sorted_val, ml, canon, node_ml);
   }
   hipLaunchKernelGGL(k_write_tree, dim3(nd_grid(nr + nint, kTB, 16384)), dim3(kTB), 0, c->stream,
                      nr, nint, root, sz, nkid, npar, canon, sorted_val, nd, parent, level);

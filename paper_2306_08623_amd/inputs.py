@@ -23,6 +23,7 @@ so these generators stand in for them:
 from __future__ import annotations
 
 import hashlib
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -258,16 +259,17 @@ def rmat(scale: int, edge_factor: int, seed: int, a: float = 0.57, b: float = 0.
 
 
 def chung_lu_weights(n: int, gamma: float, mean_degree: float, w_max: float) -> np.ndarray:
-    """Power-law expected-degree weights w_i = w_max * ((i + i0) / (1 + i0))^(-1/(gamma-1)),
-    with i0 chosen by bisection so the mean weight equals ``mean_degree``
-    (clamped to what the formula can reach)."""
+    """Power-law expected-degree weights w_i = w_max * ((i + i0) / i0)^(-1/(gamma-1))
+    (so w_0 = w_max and the tail falls off with exponent gamma), with the
+    offset i0 chosen by bisection so the mean weight equals ``mean_degree``;
+    the mean grows with i0, from 0 towards w_max (clamped at the ends)."""
     if n == 0:
         return np.zeros(0)
     expo = -1.0 / (gamma - 1.0)
     i = np.arange(n, dtype=np.float64)
 
     def mean_w(i0: float) -> float:
-        return float(np.mean(w_max * ((i + i0) / (1.0 + i0)) ** expo))
+        return float(np.mean(w_max * ((i + i0) / i0) ** expo))
 
     lo, hi = 1e-9, 1e12
     if mean_w(hi) < mean_degree:
@@ -282,7 +284,7 @@ def chung_lu_weights(n: int, gamma: float, mean_degree: float, w_max: float) -> 
             else:
                 lo = mid
         i0 = np.sqrt(lo * hi)
-    return w_max * ((i + i0) / (1.0 + i0)) ** expo
+    return w_max * ((i + i0) / i0) ** expo
 
 
 def chung_lu_edges(rng: np.random.Generator, n: int, gamma: float, mean_degree: float,
@@ -409,6 +411,24 @@ def batch_graph(i: int, base_seed: int = 4_000_000) -> tuple[CSR, int, int]:
                      clique_hi=24)
     r, s = ((2, 3), (3, 4))[(i // 2) % 2]
     return g, r, s
+
+
+def _batch_item(args):
+    i, base_seed = args
+    return batch_graph(i, base_seed)
+
+
+def batch_graphs(count: int = 4096, base_seed: int = 4_000_000,
+                 workers: int = 0) -> list[tuple[CSR, int, int]]:
+    """Graphs 0..count-1 of the mixed batch, made in ``workers`` spawned
+    processes (0: up to 16). The result does not depend on ``workers``."""
+    if workers <= 0:
+        workers = min(16, os.cpu_count() or 1)
+    if workers <= 1 or count < 64:
+        return [batch_graph(i, base_seed) for i in range(count)]
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(workers) as pool:
+        return pool.map(_batch_item, [(i, base_seed) for i in range(count)], chunksize=8)
 
 
 def serve_graph(i: int, base_seed: int = 5_000_000, m_lo: int = 1_000,

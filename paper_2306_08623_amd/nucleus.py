@@ -44,7 +44,7 @@ NONE64 = np.uint64(0xFFFFFFFFFFFFFFFF)
 EXPORTS = [
     "nd_create", "nd_destroy", "nd_load_csr", "nd_set_rs", "nd_decompose", "nd_sync",
     "nd_get_info", "nd_get_rcliques", "nd_get_counts", "nd_get_coreness", "nd_get_peel_rounds",
-    "nd_get_tree",
+    "nd_get_tree", "nd_batch_decompose", "nd_batch_get",
     "nd_status_str", "nd_last_error",
 ]
 
@@ -85,6 +85,28 @@ class Info(C.Structure):
         ("ms_count_kernel", C.c_float),
         ("ms_peel_kernel", C.c_float),
         ("device_bytes", C.c_uint64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class GraphDesc(C.Structure):
+    _fields_ = [
+        ("n", C.c_uint32), ("r", C.c_uint32), ("s", C.c_uint32),
+        ("nnz", C.c_uint64),
+        ("row_ptr", C.c_void_p),
+        ("col", C.c_void_p),
+    ]
+
+
+class GraphResult(C.Structure):
+    _fields_ = [
+        ("status", C.c_int),
+        ("k", C.c_uint32),
+        ("n_r", C.c_uint64),
+        ("n_s", C.c_uint64),
+        ("n_int", C.c_uint64),
     ]
 
     def as_dict(self) -> dict:
@@ -132,6 +154,11 @@ def load_library(path: str = LIB_PATH):
         getattr(lib, name).restype = C.c_int
     lib.nd_get_tree.argtypes = [vp, vp, vp, C.c_int]
     lib.nd_get_tree.restype = C.c_int
+    lib.nd_batch_decompose.argtypes = [vp, C.c_uint32, C.POINTER(GraphDesc), C.c_int,
+                                       C.POINTER(GraphResult)]
+    lib.nd_batch_decompose.restype = C.c_int
+    lib.nd_batch_get.argtypes = [vp, C.c_uint32, vp, vp, vp, vp, vp, C.c_int]
+    lib.nd_batch_get.restype = C.c_int
     lib.nd_status_str.argtypes = [C.c_int]
     lib.nd_status_str.restype = C.c_char_p
     lib.nd_last_error.argtypes = [vp]
@@ -291,6 +318,56 @@ class Context:
         self._check(self.lib.nd_get_tree(self.h, parent.ctypes.data if parent.size else None,
                                          level.ctypes.data if level.size else None, ND_MEM_HOST))
         return parent, level
+
+    def nd_batch_decompose(self, descs, results, where: int = ND_MEM_HOST):
+        """descs / results: ctypes arrays of GraphDesc / GraphResult."""
+        self._check(self.lib.nd_batch_decompose(self.h, len(descs), descs, where, results))
+
+    def nd_batch_get(self, i: int, res: GraphResult, r: int) -> Result:
+        n_r, n_int = res.n_r, res.n_int
+        rcl = np.zeros((n_r, r), dtype=np.uint32)
+        counts = np.zeros(n_r, dtype=np.uint32)
+        core = np.zeros(n_r, dtype=np.uint32)
+        parent = np.zeros(n_r + n_int, dtype=np.uint64)
+        level = np.zeros(n_int, dtype=np.uint32)
+
+        def p(a):
+            return a.ctypes.data if a.size else None
+        self._check(self.lib.nd_batch_get(self.h, i, p(rcl), p(counts), p(core), p(parent),
+                                          p(level), ND_MEM_HOST))
+        return Result(r=r, s=0, info=res.as_dict(), rcliques=rcl, counts=counts, coreness=core,
+                      parent=parent, level=level)
+
+    def decompose_batch(self, graphs, where: int = ND_MEM_HOST) -> list[Result]:
+        """graphs: sequence of (csr, r, s) with host CSR arrays, or, for
+        ``where=ND_MEM_DEVICE``, of (n, row_ptr, col, r, s) with device
+        tensors. Returns every graph's Result, read back to the host."""
+        G = len(graphs)
+        descs = (GraphDesc * max(G, 1))()
+        results = (GraphResult * max(G, 1))()
+        keep = []
+        rs = []
+        for i, g in enumerate(graphs):
+            if where == ND_MEM_HOST:
+                csr, r, s = g
+                rp = np.ascontiguousarray(csr.row_ptr, dtype=np.uint64)
+                col = np.ascontiguousarray(csr.col, dtype=np.uint32)
+                if col.size == 0:
+                    col = np.zeros(1, dtype=np.uint32)
+                keep.append((rp, col))
+                descs[i] = GraphDesc(csr.n, r, s, int(rp[-1]), rp.ctypes.data, col.ctypes.data)
+            else:
+                n, rp, col, r, s = g
+                keep.append((rp, col))
+                descs[i] = GraphDesc(n, r, s, int(col.numel()), rp.data_ptr(), col.data_ptr())
+            rs.append((r, s))
+        self._check(self.lib.nd_batch_decompose(self.h, G, descs, where, results))
+        out = []
+        for i in range(G):
+            res = self.nd_batch_get(i, results[i], rs[i][0])
+            res.s = rs[i][1]
+            out.append(res)
+        return out
 
     # -- convenience --------------------------------------------------------
     def decompose(self, csr, r: int, s: int) -> Result:
