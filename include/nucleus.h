@@ -201,6 +201,107 @@ nd_status nd_batch_decompose(nd_ctx *ctx, uint32_t G, const nd_graph_desc *graph
 nd_status nd_batch_get(nd_ctx *ctx, uint32_t i, uint32_t *rcliques, uint32_t *counts,
                        uint32_t *coreness, uint64_t *parent, uint32_t *level, nd_mem where);
 
+/* Device-memory estimate of decomposing one graph, from its size and a
+ * bound on its clique counts (the number of r-cliques, and of triangles
+ * where the tables need them, bounded from the degree sequence: each edge
+ * {u,v} lies in at most min(deg u, deg v) - 1 triangles). workspace: bytes
+ * the pipeline holds while the graph runs (alone or as part of a batch
+ * union, plus 4 MiB per batch); result: bytes of its outputs. Reads the CSR
+ * on the host (device inputs are copied back first). Either output may be
+ * NULL. */
+nd_status nd_estimate_footprint(const nd_graph_desc *g, nd_mem where, uint64_t *workspace,
+                                uint64_t *result);
+
+/* ---- Serving: a request loop with continuous batching ------------------
+ *
+ * A server owns `workers` device pipelines (contexts on streams of their own
+ * on one GPU) and a FIFO of requests. A request is admitted when its
+ * estimated workspace (nd_estimate_footprint) fits the free part of its
+ * pipeline's workspace share and its result fits the free part of the result
+ * share. Each pipeline repeatedly takes every admissible waiting request, up
+ * to max_batch, and decomposes them together (nd_batch_decompose), so
+ * requests that arrive while others run join the next batch of whichever
+ * pipeline frees first; the pipelines overlap on the device (uploads, tables,
+ * counting and tree phases of one run beside the peel of another; the
+ * persistent grid-barrier kernels of different pipelines run one after
+ * another). Results stay in device memory until released. Every result is
+ * exactly the one nd_decompose gives for the graph alone. */
+
+typedef struct nd_server nd_server;
+
+typedef struct nd_server_options {
+  int device;             /* HIP device ordinal                               */
+  uint32_t workers;       /* device pipelines; 0 = 2                          */
+  uint32_t max_batch;     /* most requests decomposed together; 0 = 512       */
+  uint64_t mem_budget;    /* device bytes for workspaces + held results;
+                             0 = half of the free memory at creation          */
+  int validate;           /* nonzero: check every request's CSR               */
+} nd_server_options;
+
+typedef struct nd_request_info {
+  nd_status status;       /* outcome once done (ND_E_CANCELLED if cancelled)  */
+  int done;               /* 0 = waiting or running, 1 = finished             */
+  uint32_t k;             /* max core number                                  */
+  uint64_t n_r, n_s, n_int;
+  uint64_t workspace;     /* admission estimate of its workspace (bytes)      */
+  uint64_t result_bytes;  /* device bytes its results hold                    */
+  double t_submit_ms;     /* host clock, ms since the server started          */
+  double t_start_ms;      /* its batch started                                */
+  double t_done_ms;       /* results ready                                    */
+  uint32_t batch_size;    /* requests in its batch                            */
+  uint32_t worker;        /* pipeline that ran it                             */
+} nd_request_info;
+
+/* opt may be NULL (device 0, defaults above, validation on). */
+nd_status nd_server_create(nd_server **out, const nd_server_options *opt);
+
+/* Stops accepting requests, finishes the running batches, frees everything
+ * (results not yet released included). */
+void nd_server_destroy(nd_server *srv);
+
+/* Queue one decomposition. The CSR (host or device memory per `where`) is
+ * copied before the call returns; the caller keeps ownership. Checks as in
+ * nd_batch_decompose; a request that could never be admitted (estimate above
+ * the pipeline or result share) returns ND_E_OOM. *ticket identifies it. */
+nd_status nd_server_submit(nd_server *srv, const nd_graph_desc *req, nd_mem where,
+                           uint64_t *ticket);
+
+/* State of a request without waiting (info->done tells whether it ended). */
+nd_status nd_server_poll(nd_server *srv, uint64_t ticket, nd_request_info *info);
+
+/* Wait for a request to end; timeout_ms < 0 waits without limit. Returns
+ * ND_E_STATE if the time ran out first. */
+nd_status nd_server_wait(nd_server *srv, uint64_t ticket, double timeout_ms,
+                         nd_request_info *info);
+
+/* Copy a finished request's results out, in the layout of nd_batch_get
+ * (sizes from its nd_request_info); any pointer may be NULL. */
+nd_status nd_server_get(nd_server *srv, uint64_t ticket, uint32_t *rcliques, uint32_t *counts,
+                        uint32_t *coreness, uint64_t *parent, uint32_t *level, nd_mem where);
+
+/* Free a finished request's device results and forget the ticket. */
+nd_status nd_server_release(nd_server *srv, uint64_t ticket);
+
+/* Withdraw a waiting request (it ends with ND_E_CANCELLED). A running one
+ * finishes, and its results are dropped. */
+nd_status nd_server_cancel(nd_server *srv, uint64_t ticket);
+
+typedef struct nd_server_stats {
+  uint64_t submitted, completed, failed, cancelled;
+  uint64_t batches;           /* batches run, all pipelines                     */
+  uint64_t max_batch_seen;    /* largest batch                                  */
+  uint64_t waiting, running;  /* requests now waiting / in a running batch      */
+  uint64_t result_bytes;      /* device bytes of results not yet released       */
+  uint64_t workspace_share;   /* workspace bytes each pipeline may hold         */
+  uint64_t result_share;      /* result bytes the server may hold               */
+  uint64_t overlapped;        /* requests admitted while another pipeline ran   */
+} nd_server_stats;
+
+nd_status nd_server_get_stats(nd_server *srv, nd_server_stats *out);
+
+/* Message of the server's last error (empty if none). */
+const char *nd_server_last_error(const nd_server *srv);
+
 const char *nd_status_str(nd_status st);
 
 /* Message of the last error of this context (empty string if none). With

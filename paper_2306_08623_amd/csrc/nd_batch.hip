@@ -19,7 +19,6 @@
 
 #include <algorithm>
 #include <cstring>
-#include <map>
 
 namespace {
 
@@ -191,6 +190,7 @@ static_assert(BF_LOCAL < kBatchFields, "batch slots");
 
 struct BatchGroup {
   uint32_t r = 0, s = 0;
+  int slot = 0;                           // result slots of this (r,s) pair
   std::vector<uint32_t> members;          // batch indices
   uint64_t n_r = 0, n_int = 0;
   std::vector<uint64_t> voff, roff, noff; // host copies, members + 1 entries
@@ -443,7 +443,7 @@ nd_status nd_batch_decompose(nd_ctx *c, uint32_t G, const nd_graph_desc *graphs,
   BatchState *bs = new BatchState();
   c->batch = bs;
   bs->loc.resize(G);
-  std::map<std::pair<uint32_t, uint32_t>, uint32_t> gid;
+  bool present[kBatchGroups] = {false, false, false};
   for (uint32_t i = 0; i < G; i++) results[i] = nd_graph_result{};
   for (uint32_t i = 0; i < G; i++) {
     const nd_graph_desc &d = graphs[i];
@@ -456,25 +456,30 @@ nd_status nd_batch_decompose(nd_ctx *c, uint32_t G, const nd_graph_desc *graphs,
     if (d.n == 0 && d.nnz) return fail_graph(i, ND_E_BAD_GRAPH, "edges without vertices");
     if (where == ND_MEM_HOST && (d.row_ptr[0] != 0 || d.row_ptr[d.n] != d.nnz))
       return fail_graph(i, ND_E_BAD_GRAPH, "row_ptr[0] must be 0 and row_ptr[n] must be nnz");
-    auto key = std::make_pair(d.r, d.s);
-    auto it = gid.find(key);
-    uint32_t g;
-    if (it == gid.end()) {
-      g = (uint32_t)bs->groups.size();
-      gid[key] = g;
+    // groups in the fixed order (1,2), (2,3), (3,4): each pair keeps its own
+    // result slots from one batch to the next
+    present[d.r - 1] = true;
+    bs->loc[i] = {d.r - 1, 0};
+  }
+  uint32_t gidx[kBatchGroups];
+  for (uint32_t p = 0; p < (uint32_t)kBatchGroups; p++) {
+    gidx[p] = (uint32_t)bs->groups.size();
+    if (present[p]) {
       bs->groups.emplace_back();
-      bs->groups.back().r = d.r;
-      bs->groups.back().s = d.s;
-    } else {
-      g = it->second;
+      bs->groups.back().r = p + 1;
+      bs->groups.back().s = p + 2;
+      bs->groups.back().slot = (int)p;
     }
+  }
+  for (uint32_t i = 0; i < G; i++) {
+    const uint32_t g = gidx[bs->loc[i].first];
     bs->loc[i] = {g, (uint32_t)bs->groups[g].members.size()};
     bs->groups[g].members.push_back(i);
   }
   nd_info total{};
   for (size_t g = 0; g < bs->groups.size(); g++) {
     BatchGroup &B = bs->groups[g];
-    st = run_group(c, (int)g, B, graphs, where, results);
+    st = run_group(c, B.slot, B, graphs, where, results);
     if (st != ND_OK) {
       for (uint32_t i : B.members) results[i].status = st;
       nd_batch_release(c);

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -204,6 +205,12 @@ struct nd_ctx {
   // results of the last nd_batch_decompose (nd_batch.hip)
   struct BatchState *batch = nullptr;
 
+  // contexts sharing a device under one server order their cooperative
+  // (grid-barrier) launches through a gate, so that two persistent kernels
+  // never compete for residency (nd_coop_launch)
+  struct CoopGate *gate = nullptr;
+  hipEvent_t gate_ev = nullptr;
+
   // named device buffers (grow-only)
   std::vector<DevBuf> bufs;
   uint64_t bytes_held = 0;
@@ -265,6 +272,16 @@ struct DevScalars {
 nd_status nd_fail(nd_ctx *c, nd_status st, const std::string &msg);
 void *nd_buf(nd_ctx *c, int id, size_t bytes, nd_status *st);
 nd_status nd_hip(nd_ctx *c, hipError_t e, const char *what);
+
+// cooperative launch, ordered after the previous one of any context sharing
+// the gate; `before` / `after` (may be null) are recorded around the launch
+struct CoopGate {
+  std::mutex mu;
+  hipEvent_t last = nullptr;     // completion of the last gated launch
+  const nd_ctx *owner = nullptr;
+};
+nd_status nd_coop_launch(nd_ctx *c, const void *kern, dim3 grid, dim3 block, void **args,
+                         hipEvent_t before, hipEvent_t after, const char *what);
 
 // releases the host state of the last batch (nd_batch.hip)
 void nd_batch_release(nd_ctx *c);

@@ -689,12 +689,9 @@ nd_status launch_peel(nd_ctx *c, PeelArgs &pa) {
   uint32_t nb = (uint32_t)std::max<uint64_t>(1, std::min(want, cap));
   pa.nblocks = nb;
   void *args[] = {&pa};
-  if (c->events_ok) (void)hipEventRecord(c->ev[5], c->stream);
-  nd_status st = nd_hip(c, hipLaunchCooperativeKernel(kern, dim3(nb), dim3(kPeelBlock), args, 0,
-                                                      c->stream),
+  return nd_coop_launch(c, kern, dim3(nb), dim3(kPeelBlock), args,
+                        c->events_ok ? c->ev[5] : nullptr, c->events_ok ? c->ev[6] : nullptr,
                         "peel launch");
-  if (c->events_ok) (void)hipEventRecord(c->ev[6], c->stream);
-  return st;
 }
 
 }  // namespace

@@ -551,9 +551,8 @@ nd_status nd_stage_prep(nd_ctx *c, GraphView *gv) {
                               (uint32_t)std::min<uint64_t>(2048, (n + kOrientBlock - 1) / kOrientBlock));
     oa.nblocks = nb;
     void *args[] = {&oa};
-    st = nd_hip(c, hipLaunchCooperativeKernel((const void *)k_orient, dim3(nb), dim3(kOrientBlock),
-                                              args, 0, c->stream),
-                "orientation launch");
+    st = nd_coop_launch(c, (const void *)k_orient, dim3(nb), dim3(kOrientBlock), args, nullptr,
+                        nullptr, "orientation launch");
     if (st != ND_OK) return st;
   }
   uint32_t *dgcnt = upcnt;   // reuse

@@ -44,7 +44,10 @@ NONE64 = np.uint64(0xFFFFFFFFFFFFFFFF)
 EXPORTS = [
     "nd_create", "nd_destroy", "nd_load_csr", "nd_set_rs", "nd_decompose", "nd_sync",
     "nd_get_info", "nd_get_rcliques", "nd_get_counts", "nd_get_coreness", "nd_get_peel_rounds",
-    "nd_get_tree", "nd_batch_decompose", "nd_batch_get",
+    "nd_get_tree", "nd_batch_decompose", "nd_batch_get", "nd_estimate_footprint",
+    "nd_server_create", "nd_server_destroy", "nd_server_submit", "nd_server_poll",
+    "nd_server_wait", "nd_server_get", "nd_server_release", "nd_server_cancel",
+    "nd_server_get_stats", "nd_server_last_error",
     "nd_status_str", "nd_last_error",
 ]
 
@@ -113,6 +116,44 @@ class GraphResult(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class ServerOptions(C.Structure):
+    _fields_ = [
+        ("device", C.c_int),
+        ("workers", C.c_uint32),
+        ("max_batch", C.c_uint32),
+        ("mem_budget", C.c_uint64),
+        ("validate", C.c_int),
+    ]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [
+        ("status", C.c_int),
+        ("done", C.c_int),
+        ("k", C.c_uint32),
+        ("n_r", C.c_uint64), ("n_s", C.c_uint64), ("n_int", C.c_uint64),
+        ("workspace", C.c_uint64),
+        ("result_bytes", C.c_uint64),
+        ("t_submit_ms", C.c_double),
+        ("t_start_ms", C.c_double),
+        ("t_done_ms", C.c_double),
+        ("batch_size", C.c_uint32),
+        ("worker", C.c_uint32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(name, C.c_uint64) for name in (
+        "submitted", "completed", "failed", "cancelled", "batches", "max_batch_seen",
+        "waiting", "running", "result_bytes", "workspace_share", "result_share", "overlapped")]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class NucleusError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"nucleus error {code}: {msg}")
@@ -159,6 +200,29 @@ def load_library(path: str = LIB_PATH):
     lib.nd_batch_decompose.restype = C.c_int
     lib.nd_batch_get.argtypes = [vp, C.c_uint32, vp, vp, vp, vp, vp, C.c_int]
     lib.nd_batch_get.restype = C.c_int
+    lib.nd_estimate_footprint.argtypes = [C.POINTER(GraphDesc), C.c_int, C.POINTER(C.c_uint64),
+                                          C.POINTER(C.c_uint64)]
+    lib.nd_estimate_footprint.restype = C.c_int
+    lib.nd_server_create.argtypes = [C.POINTER(vp), C.POINTER(ServerOptions)]
+    lib.nd_server_create.restype = C.c_int
+    lib.nd_server_destroy.argtypes = [vp]
+    lib.nd_server_destroy.restype = None
+    lib.nd_server_submit.argtypes = [vp, C.POINTER(GraphDesc), C.c_int, C.POINTER(C.c_uint64)]
+    lib.nd_server_submit.restype = C.c_int
+    lib.nd_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(RequestInfo)]
+    lib.nd_server_poll.restype = C.c_int
+    lib.nd_server_wait.argtypes = [vp, C.c_uint64, C.c_double, C.POINTER(RequestInfo)]
+    lib.nd_server_wait.restype = C.c_int
+    lib.nd_server_get.argtypes = [vp, C.c_uint64, vp, vp, vp, vp, vp, C.c_int]
+    lib.nd_server_get.restype = C.c_int
+    lib.nd_server_release.argtypes = [vp, C.c_uint64]
+    lib.nd_server_release.restype = C.c_int
+    lib.nd_server_cancel.argtypes = [vp, C.c_uint64]
+    lib.nd_server_cancel.restype = C.c_int
+    lib.nd_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
+    lib.nd_server_get_stats.restype = C.c_int
+    lib.nd_server_last_error.argtypes = [vp]
+    lib.nd_server_last_error.restype = C.c_char_p
     lib.nd_status_str.argtypes = [C.c_int]
     lib.nd_status_str.restype = C.c_char_p
     lib.nd_last_error.argtypes = [vp]
@@ -387,3 +451,112 @@ class Context:
 def decompose(csr, r: int, s: int, device: int = 0, **opts) -> Result:
     with Context(device=device, **opts) as ctx:
         return ctx.decompose(csr, r, s)
+
+
+def _host_desc(csr, r: int, s: int):
+    rp = np.ascontiguousarray(csr.row_ptr, dtype=np.uint64)
+    col = np.ascontiguousarray(csr.col, dtype=np.uint32)
+    if col.size == 0:
+        col = np.zeros(1, dtype=np.uint32)
+    return GraphDesc(csr.n, r, s, int(rp[-1]), rp.ctypes.data, col.ctypes.data), (rp, col)
+
+
+def estimate_footprint(csr, r: int, s: int) -> tuple[int, int]:
+    """(workspace bytes, result bytes) the library estimates for one graph."""
+    lib = load_library()
+    d, keep = _host_desc(csr, r, s)
+    ws, res = C.c_uint64(), C.c_uint64()
+    st = lib.nd_estimate_footprint(C.byref(d), ND_MEM_HOST, C.byref(ws), C.byref(res))
+    if st != ND_OK:
+        raise NucleusError(st, lib.nd_status_str(st).decode())
+    del keep
+    return ws.value, res.value
+
+
+class Server:
+    """Request loop with continuous batching (nd_server_*)."""
+
+    def __init__(self, device: int = 0, workers: int = 0, max_batch: int = 0,
+                 mem_budget: int = 0, validate: bool = True):
+        self.lib = load_library()
+        opt = ServerOptions(device, workers, max_batch, mem_budget, 1 if validate else 0)
+        h = C.c_void_p()
+        st = self.lib.nd_server_create(C.byref(h), C.byref(opt))
+        if st != ND_OK:
+            raise NucleusError(st, self.lib.nd_status_str(st).decode())
+        self.h = h
+
+    def _check(self, st: int):
+        if st != ND_OK:
+            msg = self.lib.nd_server_last_error(self.h).decode() or \
+                self.lib.nd_status_str(st).decode()
+            raise NucleusError(st, msg)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.nd_server_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, csr, r: int, s: int) -> int:
+        d, keep = _host_desc(csr, r, s)
+        t = C.c_uint64()
+        self._check(self.lib.nd_server_submit(self.h, C.byref(d), ND_MEM_HOST, C.byref(t)))
+        del keep
+        return t.value
+
+    def submit_device(self, n: int, row_ptr, col, r: int, s: int, nnz: int | None = None) -> int:
+        """row_ptr / col: device tensors; nnz defaults to col.numel()."""
+        nnz = int(col.numel()) if nnz is None else int(nnz)
+        d = GraphDesc(n, r, s, nnz, row_ptr.data_ptr(), col.data_ptr())
+        t = C.c_uint64()
+        self._check(self.lib.nd_server_submit(self.h, C.byref(d), ND_MEM_DEVICE, C.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int) -> dict:
+        info = RequestInfo()
+        self._check(self.lib.nd_server_poll(self.h, ticket, C.byref(info)))
+        return info.as_dict()
+
+    def wait(self, ticket: int, timeout_ms: float = -1.0) -> dict:
+        info = RequestInfo()
+        self._check(self.lib.nd_server_wait(self.h, ticket, timeout_ms, C.byref(info)))
+        return info.as_dict()
+
+    def get(self, ticket: int, r: int) -> Result:
+        info = self.wait(ticket)
+        n_r, n_int = info["n_r"], info["n_int"]
+        rcl = np.zeros((n_r, r), dtype=np.uint32)
+        counts = np.zeros(n_r, dtype=np.uint32)
+        core = np.zeros(n_r, dtype=np.uint32)
+        parent = np.zeros(n_r + n_int, dtype=np.uint64)
+        level = np.zeros(n_int, dtype=np.uint32)
+
+        def p(a):
+            return a.ctypes.data if a.size else None
+        self._check(self.lib.nd_server_get(self.h, ticket, p(rcl), p(counts), p(core),
+                                           p(parent), p(level), ND_MEM_HOST))
+        return Result(r=r, s=0, info=info, rcliques=rcl, counts=counts, coreness=core,
+                      parent=parent, level=level)
+
+    def release(self, ticket: int):
+        self._check(self.lib.nd_server_release(self.h, ticket))
+
+    def cancel(self, ticket: int):
+        self._check(self.lib.nd_server_cancel(self.h, ticket))
+
+    def stats(self) -> dict:
+        out = ServerStats()
+        self._check(self.lib.nd_server_get_stats(self.h, C.byref(out)))
+        return out.as_dict()
