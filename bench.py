@@ -154,6 +154,98 @@ def bench_batch(count: int, reps: int) -> dict:
     }
 
 
+def bench_serve(pool_size: int, count: int, rates: list[float], workers: int) -> dict:
+    """Serving: Poisson arrivals of requests drawn from a pool of seeded
+    Chung-Lu / R-MAT graphs (1K-2M edges, (r,s) from {(1,2),(2,3),(3,4)}).
+    For every rate: p50/p99 latency (submit to results ready, server clock)
+    and completed graphs/s. Capacity (all requests submitted at once) is
+    compared with a one-request-at-a-time server on the same requests."""
+    import threading
+
+    import numpy as np
+
+    from paper_2306_08623_amd import inputs as I
+    from paper_2306_08623_amd import nucleus
+
+    t0 = time.perf_counter()
+    pool = I.serve_graphs(pool_size)
+    print(f"[bench] serve: generated {pool_size} requests in {time.perf_counter() - t0:.1f} s "
+          f"(sum m = {sum(g.m for g, _, _ in pool)})", file=sys.stderr, flush=True)
+
+    def run(rate: float | None, n_req: int, n_workers: int, max_batch: int) -> dict:
+        rng = np.random.default_rng(12345)
+        gaps = rng.exponential(1.0 / rate, size=n_req) if rate else np.zeros(n_req)
+        arrive = np.cumsum(gaps)
+        with nucleus.Server(device=0, workers=n_workers, max_batch=max_batch) as srv:
+            tickets = [0] * n_req
+            lag = np.zeros(n_req)
+            submitted = [threading.Event() for _ in range(n_req)]
+
+            errors = []
+
+            def submitter():
+                start = time.perf_counter()
+                try:
+                    for i in range(n_req):
+                        wait = start + arrive[i] - time.perf_counter()
+                        if wait > 0:
+                            time.sleep(wait)
+                        lag[i] = time.perf_counter() - start - arrive[i]
+                        g, r, s = pool[i % len(pool)]
+                        tickets[i] = srv.submit(g, r, s)
+                        submitted[i].set()
+                except Exception as e:          # surfaced by the collector below
+                    errors.append(e)
+                    for ev in submitted:
+                        ev.set()
+
+            th = threading.Thread(target=submitter)
+            th.start()
+            infos = []
+            for i in range(n_req):           # collect and release as results come
+                submitted[i].wait()
+                if errors:
+                    raise errors[0]
+                info = srv.wait(tickets[i])
+                if info["status"] != nucleus.ND_OK:
+                    raise RuntimeError(f"request {i} failed: {info}")
+                infos.append(info)
+                srv.release(tickets[i])
+            th.join()
+            st = srv.stats()
+        lat = np.array([x["t_done_ms"] - x["t_submit_ms"] for x in infos])
+        t_first = min(x["t_submit_ms"] for x in infos)
+        t_last = max(x["t_done_ms"] for x in infos)
+        return {
+            "rate_req_s": rate, "requests": n_req,
+            "graphs_per_s": n_req / ((t_last - t_first) * 1e-3),
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_batch": float(np.mean([x["batch_size"] for x in infos])),
+            "submit_lag_p99_ms": float(np.percentile(lag, 99) * 1e3),
+            "batches": st["batches"], "overlapped": st["overlapped"],
+        }
+
+    out = {"workload": f"inputs.serve_graph(i, 5000000), i < {pool_size}: m log-uniform in "
+                       "[1K, 2M], Chung-Lu (exponent 2.3, mean degree 8) or R-MAT (edge factor "
+                       "8), (r,s) uniform over (1,2),(2,3),(3,4); Poisson arrivals (seed 12345)",
+           "pool": pool_size, "workers": workers, "sweep": []}
+    run(None, min(8, count), workers, 0)                                   # warm-up
+    for rate in rates:
+        res = run(rate, count, workers, 0)
+        out["sweep"].append(res)
+        print(f"[bench] serve: rate {rate}/s -> {res['graphs_per_s']:.1f} graphs/s, "
+              f"p50 {res['p50_ms']:.1f} ms, p99 {res['p99_ms']:.1f} ms", file=sys.stderr,
+              flush=True)
+    cap = run(None, count, workers, 0)
+    one = run(None, count, 1, 1)
+    out["capacity_graphs_per_s"] = cap["graphs_per_s"]
+    out["one_at_a_time_graphs_per_s"] = one["graphs_per_s"]
+    out["capacity_speedup"] = cap["graphs_per_s"] / one["graphs_per_s"]
+    print(f"[bench] serve: capacity {cap['graphs_per_s']:.1f} graphs/s vs one at a time "
+          f"{one['graphs_per_s']:.1f}", file=sys.stderr, flush=True)
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,6 +259,11 @@ def main() -> int:
     ap.add_argument("--batch", type=int, default=4096,
                     help="graphs in the batched-vs-one-by-one comparison (0: skip)")
     ap.add_argument("--batch-reps", type=int, default=2)
+    ap.add_argument("--serve", type=int, default=64,
+                    help="requests per rate in the serving sweep (0: skip)")
+    ap.add_argument("--serve-pool", type=int, default=64)
+    ap.add_argument("--serve-rates", default="10,100,1000,2000")
+    ap.add_argument("--serve-workers", type=int, default=2)
     ap.add_argument("--verbose", action="store_true")
     args = ap.parse_args()
 
@@ -250,6 +347,10 @@ def main() -> int:
     ctx.close()
     if args.batch:
         out["batch"] = bench_batch(args.batch, args.batch_reps)
+    if args.serve:
+        out["serve"] = bench_serve(args.serve_pool, args.serve,
+                                   [float(x) for x in args.serve_rates.split(",")],
+                                   args.serve_workers)
     if args.cpu_scale:
         out["cpu_baseline"] = cpu_baseline(r, s, args.cpu_scale)
     print(json.dumps(out), flush=True)

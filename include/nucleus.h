@@ -123,7 +123,10 @@ nd_status nd_set_rs(nd_ctx *ctx, uint32_t r, uint32_t s);
 
 /* Run the whole pipeline on the context's stream: orientation, r-clique
  * tables, s-clique counting, peel rounds with linking, tree construction and
- * canonical numbering. Blocks once on a small readback of the r-clique count
+ * canonical numbering. Two kernels of the pipeline (orientation, peel) are
+ * persistent grids that synchronise all their workgroups: while they run,
+ * no other kernel should occupy the GPU (they stop with ND_E_WATCHDOG after
+ * 20 s without progress instead of hanging). Blocks once on a small readback of the r-clique count
  * (needed to size the per-r-clique arrays) and at the end; results stay on
  * the device until read with nd_get_*. */
 nd_status nd_decompose(nd_ctx *ctx);
@@ -221,11 +224,12 @@ nd_status nd_estimate_footprint(const nd_graph_desc *g, nd_mem where, uint64_t *
  * share. Each pipeline repeatedly takes every admissible waiting request, up
  * to max_batch, and decomposes them together (nd_batch_decompose), so
  * requests that arrive while others run join the next batch of whichever
- * pipeline frees first; the pipelines overlap on the device (uploads, tables,
- * counting and tree phases of one run beside the peel of another; the
- * persistent grid-barrier kernels of different pipelines run one after
- * another). Results stay in device memory until released. Every result is
- * exactly the one nd_decompose gives for the graph alone. */
+ * pipeline frees first. The host work of one pipeline (copies at
+ * submission, checks, packing the union) overlaps the device work of
+ * another; the device runs one batch at a time, because the persistent
+ * grid-barrier kernels need all of their workgroups resident. Results stay in
+ * device memory until released. Every result is exactly the one nd_decompose
+ * gives for the graph alone. */
 
 typedef struct nd_server nd_server;
 

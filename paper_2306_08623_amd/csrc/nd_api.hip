@@ -64,23 +64,10 @@ void *nd_buf(nd_ctx *c, int id, size_t bytes, nd_status *st) {
 
 nd_status nd_coop_launch(nd_ctx *c, const void *kern, dim3 grid, dim3 block, void **args,
                          hipEvent_t before, hipEvent_t after, const char *what) {
-  std::unique_lock<std::mutex> lk;
-  if (c->gate) {
-    lk = std::unique_lock<std::mutex>(c->gate->mu);
-    if (c->gate->last && c->gate->owner != c) {
-      nd_status st = nd_hip(c, hipStreamWaitEvent(c->stream, c->gate->last, 0), "gate wait");
-      if (st != ND_OK) return st;
-    }
-  }
   if (before) (void)hipEventRecord(before, c->stream);
   nd_status st =
       nd_hip(c, hipLaunchCooperativeKernel(kern, grid, block, args, 0, c->stream), what);
   if (after) (void)hipEventRecord(after, c->stream);
-  if (c->gate && st == ND_OK) {
-    st = nd_hip(c, hipEventRecord(c->gate_ev, c->stream), "gate record");
-    c->gate->last = c->gate_ev;
-    c->gate->owner = c;
-  }
   return st;
 }
 
@@ -178,7 +165,6 @@ void nd_destroy(nd_ctx *c) {
     if (b.p) (void)hipFree(b.p);
   for (int i = 0; i < 10; i++)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
-  if (c->gate_ev) (void)hipEventDestroy(c->gate_ev);
   delete c;
 }
 

@@ -194,6 +194,10 @@ struct BatchGroup {
   std::vector<uint32_t> members;          // batch indices
   uint64_t n_r = 0, n_int = 0;
   std::vector<uint64_t> voff, roff, noff; // host copies, members + 1 entries
+  std::vector<uint64_t> eoff;             // CSR-slot offsets, members + 1 entries
+  // union CSR packed on the host by the plan (host inputs only)
+  std::vector<uint64_t> hrp;
+  std::vector<uint32_t> hcol;
   // device results of the group (context slots, valid until the next batch)
   uint32_t *rcl = nullptr, *cnt0 = nullptr, *core = nullptr, *level = nullptr;
   uint64_t *parent = nullptr;
@@ -203,6 +207,8 @@ struct BatchGroup {
 struct BatchState {
   std::vector<BatchGroup> groups;
   std::vector<std::pair<uint32_t, uint32_t>> loc;   // batch index -> (group, position)
+  const nd_graph_desc *graphs = nullptr;            // the caller's, during execution
+  nd_mem where = ND_MEM_HOST;
 };
 
 void nd_batch_release(nd_ctx *c) {
@@ -210,20 +216,14 @@ void nd_batch_release(nd_ctx *c) {
   c->batch = nullptr;
 }
 
+void nd_batch_state_free(BatchState *bs) { delete bs; }
+
 static nd_status run_group(nd_ctx *c, int gi, BatchGroup &B, const nd_graph_desc *graphs,
                            nd_mem where, nd_graph_result *results) {
   nd_status st = ND_OK;
   const uint32_t G = (uint32_t)B.members.size();
-  B.voff.assign(G + 1, 0);
-  std::vector<uint64_t> eoff(G + 1, 0);
-  for (uint32_t j = 0; j < G; j++) {
-    const nd_graph_desc &d = graphs[B.members[j]];
-    B.voff[j + 1] = B.voff[j] + d.n;
-    eoff[j + 1] = eoff[j] + d.nnz;
-  }
+  const std::vector<uint64_t> &eoff = B.eoff;
   const uint64_t n_tot = B.voff[G], nnz_tot = eoff[G];
-  if (n_tot >= 0xFFFFFFFFull || nnz_tot / 2 >= 0xFFFFFFFFull)
-    return nd_fail(c, ND_E_UNSUPPORTED, "a batch group exceeds 32-bit vertex or edge ids");
   uint64_t *rp = (uint64_t *)nd_buf(c, B_RP, (n_tot + 1) * 8, &st);
   if (!rp) return st;
   uint32_t *col = (uint32_t *)nd_buf(c, B_COL, std::max<uint64_t>(nnz_tot, 1) * 4, &st);
@@ -240,31 +240,23 @@ static nd_status run_group(nd_ctx *c, int gi, BatchGroup &B, const nd_graph_desc
                                        c->stream),
                      "batch descriptors")) != ND_OK)
       return st;
-    hipLaunchKernelGGL(k_gather_union, dim3(16, std::min<uint32_t>(G, 8192)), dim3(256), 0, c->stream, dm, G,
-                       (uint32_t)n_tot, nnz_tot, rp, col);
+    hipLaunchKernelGGL(k_gather_union, dim3(16, std::min<uint32_t>(G, 8192)), dim3(256), 0,
+                       c->stream, dm, G, (uint32_t)n_tot, nnz_tot, rp, col);
     if ((st = nd_hip(c, hipGetLastError(), "union gather")) != ND_OK) return st;
     // the descriptor upload reads pageable host memory
     if ((st = nd_hip(c, hipStreamSynchronize(c->stream), "union gather")) != ND_OK) return st;
   } else {
-    std::vector<uint64_t> hrp(n_tot + 1);
-    std::vector<uint32_t> hcol(std::max<uint64_t>(nnz_tot, 1));
-    for (uint32_t j = 0; j < G; j++) {
-      const nd_graph_desc &d = graphs[B.members[j]];
-      for (uint32_t u = 0; u < d.n; u++) hrp[B.voff[j] + u] = eoff[j] + d.row_ptr[u];
-      const uint32_t vo = (uint32_t)B.voff[j];
-      for (uint64_t x = 0; x < d.nnz; x++)
-        hcol[eoff[j] + x] = d.col[x] < d.n ? d.col[x] + vo : ND_NONE;
-    }
-    hrp[n_tot] = nnz_tot;
-    if ((st = nd_hip(c, hipMemcpyAsync(rp, hrp.data(), (n_tot + 1) * 8, hipMemcpyHostToDevice,
+    if ((st = nd_hip(c, hipMemcpyAsync(rp, B.hrp.data(), (n_tot + 1) * 8, hipMemcpyHostToDevice,
                                        c->stream),
                      "union row_ptr")) != ND_OK)
       return st;
-    if (nnz_tot && (st = nd_hip(c, hipMemcpyAsync(col, hcol.data(), nnz_tot * 4,
+    if (nnz_tot && (st = nd_hip(c, hipMemcpyAsync(col, B.hcol.data(), nnz_tot * 4,
                                                   hipMemcpyHostToDevice, c->stream),
                                 "union col")) != ND_OK)
       return st;
     if ((st = nd_hip(c, hipStreamSynchronize(c->stream), "union upload")) != ND_OK) return st;
+    std::vector<uint64_t>().swap(B.hrp);
+    std::vector<uint32_t>().swap(B.hcol);
   }
   c->n = (uint32_t)n_tot;
   c->nnz = nnz_tot;
@@ -419,32 +411,30 @@ static void add_info(nd_info &T, const nd_info &I) {
   T.ms_peel_kernel += I.ms_peel_kernel;
 }
 
-extern "C" {
-
-nd_status nd_batch_decompose(nd_ctx *c, uint32_t G, const nd_graph_desc *graphs, nd_mem where,
-                             nd_graph_result *results) {
-  if (!c) return ND_E_INVALID_ARG;
-  nd_status st = nd_hip(c, hipSetDevice(c->device), "hipSetDevice");
-  if (st != ND_OK) return st;
-  c->last_error.clear();
-  nd_batch_release(c);
-  c->have_graph = false;
-  c->decomposed = false;
-  c->info_valid = false;
-  if (G && (!graphs || !results))
-    return nd_fail(c, ND_E_INVALID_ARG, "NULL graph descriptors or results");
-  if (where != ND_MEM_HOST && where != ND_MEM_DEVICE)
-    return nd_fail(c, ND_E_INVALID_ARG, "bad memory kind");
-  auto fail_graph = [&](uint32_t i, nd_status code, const char *what) {
-    nd_batch_release(c);
-    results[i].status = code;
-    return nd_fail(c, code, "graph " + std::to_string(i) + ": " + what);
-  };
-  BatchState *bs = new BatchState();
-  c->batch = bs;
-  bs->loc.resize(G);
-  bool present[kBatchGroups] = {false, false, false};
+// Host half of a batch: checks, grouping by (r,s) and, for host inputs, the
+// union CSRs packed on the host. Needs no device.
+nd_status nd_batch_plan(uint32_t G, const nd_graph_desc *graphs, nd_mem where,
+                        nd_graph_result *results, BatchState **out, std::string *err) {
+  *out = nullptr;
+  if (G && (!graphs || !results)) {
+    *err = "NULL graph descriptors or results";
+    return ND_E_INVALID_ARG;
+  }
+  if (where != ND_MEM_HOST && where != ND_MEM_DEVICE) {
+    *err = "bad memory kind";
+    return ND_E_INVALID_ARG;
+  }
   for (uint32_t i = 0; i < G; i++) results[i] = nd_graph_result{};
+  BatchState *bs = new BatchState();
+  bs->loc.resize(G);
+  bs->where = where;
+  auto fail_graph = [&](uint32_t i, nd_status code, const char *what) {
+    delete bs;
+    results[i].status = code;
+    *err = "graph " + std::to_string(i) + ": " + what;
+    return code;
+  };
+  bool present[kBatchGroups] = {false, false, false};
   for (uint32_t i = 0; i < G; i++) {
     const nd_graph_desc &d = graphs[i];
     if (d.r < 1 || d.s <= d.r) return fail_graph(i, ND_E_INVALID_ARG, "need 1 <= r < s");
@@ -476,10 +466,58 @@ nd_status nd_batch_decompose(nd_ctx *c, uint32_t G, const nd_graph_desc *graphs,
     bs->loc[i] = {g, (uint32_t)bs->groups[g].members.size()};
     bs->groups[g].members.push_back(i);
   }
+  for (BatchGroup &B : bs->groups) {
+    const uint32_t M = (uint32_t)B.members.size();
+    B.voff.assign(M + 1, 0);
+    B.eoff.assign(M + 1, 0);
+    for (uint32_t j = 0; j < M; j++) {
+      const nd_graph_desc &d = graphs[B.members[j]];
+      B.voff[j + 1] = B.voff[j] + d.n;
+      B.eoff[j + 1] = B.eoff[j] + d.nnz;
+    }
+    const uint64_t n_tot = B.voff[M], nnz_tot = B.eoff[M];
+    if (n_tot >= 0xFFFFFFFFull || nnz_tot / 2 >= 0xFFFFFFFFull) {
+      for (uint32_t i : B.members) results[i].status = ND_E_UNSUPPORTED;
+      delete bs;
+      *err = "a batch group exceeds 32-bit vertex or edge ids";
+      return ND_E_UNSUPPORTED;
+    }
+    if (where == ND_MEM_HOST) {
+      // members whose columns leave 0..n-1 get entries the validation rejects
+      B.hrp.resize(n_tot + 1);
+      B.hcol.resize(std::max<uint64_t>(nnz_tot, 1));
+      for (uint32_t j = 0; j < M; j++) {
+        const nd_graph_desc &d = graphs[B.members[j]];
+        for (uint32_t u = 0; u < d.n; u++) B.hrp[B.voff[j] + u] = B.eoff[j] + d.row_ptr[u];
+        const uint32_t vo = (uint32_t)B.voff[j];
+        uint32_t *dst = B.hcol.data() + B.eoff[j];
+        for (uint64_t x = 0; x < d.nnz; x++) dst[x] = d.col[x] < d.n ? d.col[x] + vo : ND_NONE;
+      }
+      B.hrp[n_tot] = nnz_tot;
+    }
+  }
+  *out = bs;
+  return ND_OK;
+}
+
+// Device half: takes ownership of the plan (kept as the context's batch on
+// success). `graphs` must be the descriptors the plan was made from.
+nd_status nd_batch_execute(nd_ctx *c, BatchState *bs, const nd_graph_desc *graphs,
+                           nd_graph_result *results) {
+  nd_status st = nd_hip(c, hipSetDevice(c->device), "hipSetDevice");
+  nd_batch_release(c);
+  c->have_graph = false;
+  c->decomposed = false;
+  c->info_valid = false;
+  if (st != ND_OK) {
+    delete bs;
+    return st;
+  }
+  c->batch = bs;
   nd_info total{};
   for (size_t g = 0; g < bs->groups.size(); g++) {
     BatchGroup &B = bs->groups[g];
-    st = run_group(c, B.slot, B, graphs, where, results);
+    st = run_group(c, B.slot, B, graphs, bs->where, results);
     if (st != ND_OK) {
       for (uint32_t i : B.members) results[i].status = st;
       nd_batch_release(c);
@@ -499,6 +537,23 @@ nd_status nd_batch_decompose(nd_ctx *c, uint32_t G, const nd_graph_desc *graphs,
   c->info = total;
   c->info_valid = true;
   return ND_OK;
+}
+
+extern "C" {
+
+nd_status nd_batch_decompose(nd_ctx *c, uint32_t G, const nd_graph_desc *graphs, nd_mem where,
+                             nd_graph_result *results) {
+  if (!c) return ND_E_INVALID_ARG;
+  c->last_error.clear();
+  nd_batch_release(c);
+  c->have_graph = false;
+  c->decomposed = false;
+  c->info_valid = false;
+  BatchState *bs = nullptr;
+  std::string err;
+  nd_status st = nd_batch_plan(G, graphs, where, results, &bs, &err);
+  if (st != ND_OK) return nd_fail(c, st, err);
+  return nd_batch_execute(c, bs, graphs, results);
 }
 
 nd_status nd_batch_get(nd_ctx *c, uint32_t i, uint32_t *rcliques, uint32_t *counts,

@@ -183,6 +183,8 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+struct BatchState;
+
 struct nd_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -203,13 +205,7 @@ struct nd_ctx {
   bool info_valid = false;   // info holds the last decomposition or batch
 
   // results of the last nd_batch_decompose (nd_batch.hip)
-  struct BatchState *batch = nullptr;
-
-  // contexts sharing a device under one server order their cooperative
-  // (grid-barrier) launches through a gate, so that two persistent kernels
-  // never compete for residency (nd_coop_launch)
-  struct CoopGate *gate = nullptr;
-  hipEvent_t gate_ev = nullptr;
+  BatchState *batch = nullptr;
 
   // named device buffers (grow-only)
   std::vector<DevBuf> bufs;
@@ -273,18 +269,21 @@ nd_status nd_fail(nd_ctx *c, nd_status st, const std::string &msg);
 void *nd_buf(nd_ctx *c, int id, size_t bytes, nd_status *st);
 nd_status nd_hip(nd_ctx *c, hipError_t e, const char *what);
 
-// cooperative launch, ordered after the previous one of any context sharing
-// the gate; `before` / `after` (may be null) are recorded around the launch
-struct CoopGate {
-  std::mutex mu;
-  hipEvent_t last = nullptr;     // completion of the last gated launch
-  const nd_ctx *owner = nullptr;
-};
+// cooperative (grid-barrier) launch on the context's stream; `before` /
+// `after` (may be null) are recorded around it
 nd_status nd_coop_launch(nd_ctx *c, const void *kern, dim3 grid, dim3 block, void **args,
                          hipEvent_t before, hipEvent_t after, const char *what);
 
 // releases the host state of the last batch (nd_batch.hip)
 void nd_batch_release(nd_ctx *c);
+
+// a batch split in its host half (checks, grouping, union packing; no
+// device) and its device half (nd_batch.hip); execute takes ownership
+nd_status nd_batch_plan(uint32_t G, const nd_graph_desc *graphs, nd_mem where,
+                        nd_graph_result *results, BatchState **out, std::string *err);
+nd_status nd_batch_execute(nd_ctx *c, BatchState *bs, const nd_graph_desc *graphs,
+                           nd_graph_result *results);
+void nd_batch_state_free(BatchState *bs);
 
 // the whole decomposition of the graph held in the context (nd_api.hip)
 nd_status nd_run_pipeline(nd_ctx *c);

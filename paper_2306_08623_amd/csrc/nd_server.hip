@@ -5,7 +5,9 @@
 // free takes every admissible request at the head of the FIFO (up to
 // max_batch) and decomposes them as one batch; requests arriving meanwhile
 // wait for the next free pipeline, so batches form continuously from what
-// has arrived. Admission uses the footprint estimate of nd_estimate_footprint:
+// has arrived. The pipelines' host work (copies at submission, checks,
+// union packing, admission) overlaps the device work of another pipeline;
+// the device itself runs one batch at a time. Admission uses the footprint estimate of nd_estimate_footprint:
 // a pipeline's batch stays within its workspace share, and the results held
 // on the device (until the client releases them) stay within the result
 // share. Results live in stream-ordered device allocations, so releasing
@@ -91,7 +93,10 @@ struct nd_server {
   std::vector<nd_ctx *> ctxs;
   std::vector<hipStream_t> streams;
   hipStream_t io = nullptr;  // copies out and frees
-  CoopGate gate;
+  // device work runs one batch at a time: the persistent grid-barrier
+  // kernels need every workgroup resident, so nothing else of the server may
+  // occupy the compute units beside them
+  std::mutex device_mu;
   Clock::time_point t0;
   nd_server_stats stats{};
   std::string last_error;
@@ -111,6 +116,8 @@ nd_status srv_fail(nd_server *S, nd_status st, const std::string &msg) {
 }
 
 // Decompose one batch on pipeline w; fills every request's info and results.
+// The host half (checks, union packing) runs outside the device lock, so one
+// pipeline prepares its batch while another's runs on the device.
 void run_batch(nd_server *S, uint32_t w, std::vector<Request *> &batch) {
   nd_ctx *c = S->ctxs[w];
   const uint32_t G = (uint32_t)batch.size();
@@ -121,11 +128,19 @@ void run_batch(nd_server *S, uint32_t w, std::vector<Request *> &batch) {
     descs[i] = nd_graph_desc{q->n, q->r, q->s, q->nnz, q->rp.data(),
                              q->col.empty() ? nullptr : q->col.data()};
   }
-  nd_status st = nd_batch_decompose(c, G, descs.data(), ND_MEM_HOST, results.data());
+  BatchState *plan = nullptr;
+  std::string err;
+  nd_status st = nd_batch_plan(G, descs.data(), ND_MEM_HOST, results.data(), &plan, &err);
+  std::unique_lock<std::mutex> dev(S->device_mu);
+  if (st == ND_OK) {
+    st = nd_batch_execute(c, plan, descs.data(), results.data());
+    err = c->last_error;
+  }
   if (st != ND_OK && G > 1) {
     // one member's error (a bad graph, or an estimate too small for the
     // union) fails the whole union: run the members one by one so that only
     // the faulty one fails
+    dev.unlock();
     for (uint32_t i = 0; i < G; i++) {
       std::vector<Request *> one{batch[i]};
       run_batch(S, w, one);
@@ -133,10 +148,10 @@ void run_batch(nd_server *S, uint32_t w, std::vector<Request *> &batch) {
     return;
   }
   if (st != ND_OK) {
-    std::string msg = c->last_error;
+    dev.unlock();
     for (Request *q : batch) q->info.status = st;
     std::lock_guard<std::mutex> lk(S->mu);
-    S->last_error = msg;
+    S->last_error = err;
     return;
   }
   for (uint32_t i = 0; i < G; i++) {
@@ -339,13 +354,6 @@ nd_status nd_server_create(nd_server **out, const nd_server_options *opt) {
     if (rc != ND_OK) {
       nd_server_destroy(S);
       return rc;
-    }
-    c->gate = &S->gate;
-    if (hipEventCreateWithFlags(&c->gate_ev, hipEventDisableTiming) != hipSuccess) {
-      (void)hipGetLastError();
-      S->ctxs.push_back(c);
-      nd_server_destroy(S);
-      return ND_E_DEVICE;
     }
     S->ctxs.push_back(c);
   }

@@ -450,6 +450,24 @@ def serve_graph(i: int, base_seed: int = 5_000_000, m_lo: int = 1_000,
     return g, r, s
 
 
+def _serve_item(args):
+    i, base_seed = args
+    return serve_graph(i, base_seed)
+
+
+def serve_graphs(count: int, base_seed: int = 5_000_000,
+                 workers: int = 0) -> list[tuple[CSR, int, int]]:
+    """Requests 0..count-1 of the serving stream, made in ``workers`` spawned
+    processes (0: up to 16). The result does not depend on ``workers``."""
+    if workers <= 0:
+        workers = min(16, os.cpu_count() or 1)
+    if workers <= 1 or count < 8:
+        return [serve_graph(i, base_seed) for i in range(count)]
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(workers) as pool:
+        return pool.map(_serve_item, [(i, base_seed) for i in range(count)], chunksize=1)
+
+
 # ---------------------------------------------------------------------------
 # Binary CSR files (for the C++ profiling driver)
 # ---------------------------------------------------------------------------
