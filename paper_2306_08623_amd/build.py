@@ -17,9 +17,11 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnucleus.so")
 DRIVER = os.path.join(HERE, "nd_profile")
+COPY = os.path.join(HERE, "nd_copy")
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+HIP_FEATURES = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -70,8 +72,17 @@ def build(verbose: bool = False) -> str:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("driver build failed")
     os.replace(drv_tmp, DRIVER)
+    # counter calibration: a plain copy kernel of known size
+    copy_tmp = COPY + f".tmp{os.getpid()}"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-O3", "-std=c++17", *HIP_FEATURES,
+           os.path.join(HERE, "nd_copy.hip"), f"-Wl,-rpath,{rpath}", "-o", copy_tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("copy tool build failed")
+    os.replace(copy_tmp, COPY)
     if verbose:
-        print("built", LIB, "and", DRIVER)
+        print("built", LIB, ",", DRIVER, "and", COPY)
     return LIB
 
 
