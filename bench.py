@@ -38,9 +38,9 @@ HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes of the dominant kernels ("Roofline"):
 #   peel+link kernel: bytes per (r-clique, s-clique) visit and per peeled
 #   r-clique; counting kernel: bytes per listed s-clique.
-PEEL_BYTES_PER_VISIT = {(1, 2): 16, (2, 3): 40, (3, 4): 60}
-PEEL_BYTES_PER_RCLIQUE = {(1, 2): 20, (2, 3): 24, (3, 4): 28}
-COUNT_BYTES_PER_SCLIQUE = {(1, 2): 0, (2, 3): 36, (3, 4): 64}
+PEEL_BYTES_PER_VISIT = {(1, 2): 16, (2, 3): 40, (3, 4): 60, (2, 4): 96}
+PEEL_BYTES_PER_RCLIQUE = {(1, 2): 20, (2, 3): 24, (3, 4): 28, (2, 4): 28}
+COUNT_BYTES_PER_SCLIQUE = {(1, 2): 0, (2, 3): 36, (3, 4): 64, (2, 4): 72}
 
 
 PROFILE = os.path.join(ROOT, "profiles", "k_peel_rmat18_34.txt")

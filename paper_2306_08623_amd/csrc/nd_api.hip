@@ -213,8 +213,7 @@ nd_status nd_load_csr(nd_ctx *c, uint32_t n, uint64_t nnz, const uint64_t *row_p
 nd_status nd_set_rs(nd_ctx *c, uint32_t r, uint32_t s) {
   if (!c) return ND_E_INVALID_ARG;
   if (r < 1 || s <= r) return nd_fail(c, ND_E_INVALID_ARG, "need 1 <= r < s");
-  bool ok = (r == 1 && s == 2) || (r == 2 && s == 3) || (r == 3 && s == 4);
-  if (!ok) return nd_fail(c, ND_E_UNSUPPORTED, "this (r,s) pair is not built");
+  if (!nd_rs_supported(r, s)) return nd_fail(c, ND_E_UNSUPPORTED, "this (r,s) pair is not built");
   c->r = r;
   c->s = s;
   c->decomposed = false;
@@ -235,7 +234,9 @@ static nd_status check_device_status(nd_ctx *c, DevScalars *host) {
   if (host->status & ND_DERR_LINKQ)
     return nd_fail(c, ND_E_OOM, "link spill queue overflowed");
   if (host->status & ND_DERR_OVERFLOW)
-    return nd_fail(c, ND_E_UNSUPPORTED, "an oriented out-neighbourhood exceeds the listing buffer");
+    return nd_fail(c, ND_E_UNSUPPORTED,
+                   "a listing buffer or a 32-bit work range was exceeded (an oriented "
+                   "out-neighbourhood, or the (2,4) probe range of one edge)");
   if (host->status & ND_DERR_BADGRAPH) return nd_fail(c, ND_E_BAD_GRAPH, "bad graph");
   return ND_OK;
 }

@@ -434,30 +434,31 @@ nd_status nd_batch_plan(uint32_t G, const nd_graph_desc *graphs, nd_mem where,
     *err = "graph " + std::to_string(i) + ": " + what;
     return code;
   };
-  bool present[kBatchGroups] = {false, false, false};
+  bool present[kBatchGroups] = {false, false, false, false};
   for (uint32_t i = 0; i < G; i++) {
     const nd_graph_desc &d = graphs[i];
     if (d.r < 1 || d.s <= d.r) return fail_graph(i, ND_E_INVALID_ARG, "need 1 <= r < s");
-    const bool ok = (d.r == 1 && d.s == 2) || (d.r == 2 && d.s == 3) || (d.r == 3 && d.s == 4);
-    if (!ok) return fail_graph(i, ND_E_UNSUPPORTED, "this (r,s) pair is not built");
+    if (!nd_rs_supported(d.r, d.s))
+      return fail_graph(i, ND_E_UNSUPPORTED, "this (r,s) pair is not built");
     if (!d.row_ptr || (d.nnz && !d.col))
       return fail_graph(i, ND_E_INVALID_ARG, "NULL row_ptr or col");
     if (d.nnz & 1) return fail_graph(i, ND_E_BAD_GRAPH, "nnz is odd");
     if (d.n == 0 && d.nnz) return fail_graph(i, ND_E_BAD_GRAPH, "edges without vertices");
     if (where == ND_MEM_HOST && (d.row_ptr[0] != 0 || d.row_ptr[d.n] != d.nnz))
       return fail_graph(i, ND_E_BAD_GRAPH, "row_ptr[0] must be 0 and row_ptr[n] must be nnz");
-    // groups in the fixed order (1,2), (2,3), (3,4): each pair keeps its own
-    // result slots from one batch to the next
-    present[d.r - 1] = true;
-    bs->loc[i] = {d.r - 1, 0};
+    // groups in the fixed order (1,2), (2,3), (3,4), (2,4): each pair keeps
+    // its own result slots from one batch to the next
+    const int pi = nd_rs_index(d.r, d.s);
+    present[pi] = true;
+    bs->loc[i] = {(uint32_t)pi, 0};
   }
   uint32_t gidx[kBatchGroups];
   for (uint32_t p = 0; p < (uint32_t)kBatchGroups; p++) {
     gidx[p] = (uint32_t)bs->groups.size();
     if (present[p]) {
       bs->groups.emplace_back();
-      bs->groups.back().r = p + 1;
-      bs->groups.back().s = p + 2;
+      bs->groups.back().r = p == 3 ? 2 : p + 1;
+      bs->groups.back().s = p == 3 ? 4 : p + 2;
       bs->groups.back().slot = (int)p;
     }
   }

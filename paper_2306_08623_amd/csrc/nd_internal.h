@@ -40,11 +40,14 @@ struct GraphView {
   const uint64_t *dgp;       // [n+1] oriented out-CSR offsets
   const uint32_t *dgc;       // [m] out-neighbours, ascending vertex id
   const uint32_t *dge;       // [m] edge id of each out-slot
-  // edge -> triangle lists (only for r = 3)
+  // edge -> triangle lists (r = 3, and (r,s) = (2,4))
   const uint64_t *wp;        // [m+1] offsets of W(e), the common neighbours of e
   const uint32_t *wc;        // [3 n_tri] W entries (third vertex), ascending per edge
   const uint32_t *wt;        // [3 n_tri] triangle id of each W entry
   const uint32_t *te;        // [3 n_tri] (e_ab, e_ac, e_bc) of triangle (a<b<c)
+  // (2,4) only: running sum over all W entries of the probe length of the
+  // entry's triangle (shortest W list among its three edges); [3 n_tri + 1]
+  const uint64_t *wg;
 };
 
 // ---------------------------------------------------------------------------
@@ -235,13 +238,21 @@ enum BufId : int {
   B_SCAL, B_TMP64, B_TMP32A, B_TMP32B, B_TMP32C, B_TMP32D,
   B_SORTK0, B_SORTK1, B_SORTV0, B_SORTV1, B_HIST,
   B_PARENT, B_LEVEL, B_RCL, B_GCACHE, B_ACNT, B_NODEML, B_SORTOFF,
-  B_BATCHDESC,
+  B_BATCHDESC, B_WG, B_W24L,
   B_COUNT
 };
 
+// the (r,s) pairs whose peel is built; index of a pair's batch slots
+inline bool nd_rs_supported(uint32_t r, uint32_t s) {
+  return (r == 1 && s == 2) || (r == 2 && s == 3) || (r == 3 && s == 4) || (r == 2 && s == 4);
+}
+inline int nd_rs_index(uint32_t r, uint32_t s) {
+  return (r == 2 && s == 4) ? 3 : (int)r - 1;
+}
+
 // batch arena: per (r,s) group, kBatchFields grow-only slots after B_COUNT
 constexpr int kBatchFields = 10;
-constexpr int kBatchGroups = 3;
+constexpr int kBatchGroups = 4;   // (1,2), (2,3), (3,4), (2,4)
 inline int nd_batch_slot(int group, int field) { return B_COUNT + group * kBatchFields + field; }
 
 // device scalars block (one per context)

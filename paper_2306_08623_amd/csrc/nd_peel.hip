@@ -308,6 +308,87 @@ struct Shape<3, 4> {
   }
 };
 
+// (2,4): R = edge e = {u, v}. A 4-clique {u, v, w, x} containing e is a
+// triangle t = {u, v, w} on e (an entry of W(e)) extended by a common
+// neighbour x of t; probe entries are, for every triangle t of e in W(e)
+// order, the entries of t's shortest W list, as one flat range (wg holds the
+// running sums). Each 4-clique is taken from the triangle with the smaller
+// of its two extra vertices (x > w), so it is met once. The other five edges
+// are {u,w}, {v,w} (from t), {u,x}, {v,x} (from triangle {u,v,x}, x's entry
+// in W(e)) and {w,x} (from triangle {u,w,x} or {v,w,x}).
+template <>
+struct Shape<2, 4> {
+  static constexpr int kOthers = 5;
+  __device__ static uint32_t len(const GraphView &g, uint32_t R) {
+    return (uint32_t)(g.wg[g.wp[R + 1]] - g.wg[g.wp[R]]);
+  }
+  __device__ static bool visit(const GraphView &g, uint32_t R, uint32_t i, uint32_t *o) {
+    const uint64_t b = g.wp[R], f = g.wp[R + 1];
+    const uint64_t target = g.wg[b] + i;
+    // the W entry whose probe range holds `target`: last p with wg[p] <= target
+    uint64_t lo = b, hi = f;
+    while (hi - lo > 1) {
+      const uint64_t mid = (lo + hi) >> 1;
+      if (g.wg[mid] <= target) lo = mid;
+      else hi = mid;
+    }
+    const uint64_t pt = lo;
+    const uint32_t w = g.wc[pt];
+    const uint32_t t = g.wt[pt];
+    const uint64_t j = target - g.wg[pt];
+    // t's edges: R and the two edges to w
+    uint32_t ea = g.te[3ull * t], eb = g.te[3ull * t + 1], ec = g.te[3ull * t + 2];
+    uint32_t x1, x2;   // the edges of t other than R
+    if (ea == R) { x1 = eb; x2 = ec; }
+    else if (eb == R) { x1 = ea; x2 = ec; }
+    else { x1 = ea; x2 = eb; }
+    // probe t's shortest list (R's own list W(e) or one of x1, x2)
+    const uint64_t sR = f - b, s1 = g.wp[x1 + 1] - g.wp[x1], s2 = g.wp[x2 + 1] - g.wp[x2];
+    uint64_t pR, p1;
+    uint32_t x;
+    if (sR <= s1 && sR <= s2) {
+      pR = b + j;
+      x = g.wc[pR];
+      if (x <= w) return false;
+      p1 = find_u32<uint64_t>(g.wc, g.wp[x1], g.wp[x1 + 1], x);
+      if (p1 == g.wp[x1 + 1]) return false;
+      const uint64_t p2 = find_u32<uint64_t>(g.wc, g.wp[x2], g.wp[x2 + 1], x);
+      if (p2 == g.wp[x2 + 1]) return false;
+    } else {
+      const uint32_t ep = s1 <= s2 ? x1 : x2, eo = s1 <= s2 ? x2 : x1;
+      const uint64_t pp = g.wp[ep] + j;
+      x = g.wc[pp];
+      if (x <= w) return false;
+      const uint64_t po = find_u32<uint64_t>(g.wc, g.wp[eo], g.wp[eo + 1], x);
+      if (po == g.wp[eo + 1]) return false;
+      pR = find_u32<uint64_t>(g.wc, b, f, x);
+      if (pR == f) return false;
+      p1 = ep == x1 ? pp : po;
+    }
+    // triangle {u,v,x}: its edges other than R are {u,x}, {v,x}
+    const uint32_t tx = g.wt[pR];
+    uint32_t ya = g.te[3ull * tx], yb = g.te[3ull * tx + 1], yc = g.te[3ull * tx + 2];
+    uint32_t y1, y2;
+    if (ya == R) { y1 = yb; y2 = yc; }
+    else if (yb == R) { y1 = ya; y2 = yc; }
+    else { y1 = ya; y2 = yb; }
+    // triangle on x1 with x: its edges are x1, one of {y1, y2}, and {w,x}
+    const uint32_t tw = g.wt[p1];
+    uint32_t wx = ND_NONE;
+    for (int q = 0; q < 3; q++) {
+      const uint32_t z = g.te[3ull * tw + q];
+      if (z != x1 && z != y1 && z != y2) wx = z;
+    }
+    if (wx == ND_NONE) return false;   // unreachable for consistent tables
+    o[0] = x1;
+    o[1] = x2;
+    o[2] = y1;
+    o[3] = y2;
+    o[4] = wx;
+    return true;
+  }
+};
+
 // ---------------------------------------------------------------------------
 // redundant-link filter
 // ---------------------------------------------------------------------------
@@ -754,5 +835,6 @@ nd_status nd_stage_peel(nd_ctx *c, const GraphView &g) {
   if (r == 1 && s == 2) return launch_peel<1, 2>(c, pa);
   if (r == 2 && s == 3) return launch_peel<2, 3>(c, pa);
   if (r == 3 && s == 4) return launch_peel<3, 4>(c, pa);
+  if (r == 2 && s == 4) return launch_peel<2, 4>(c, pa);
   return nd_fail(c, ND_E_UNSUPPORTED, "peeling for this (r,s) is not built");
 }

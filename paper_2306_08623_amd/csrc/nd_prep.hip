@@ -470,6 +470,31 @@ nd_status nd_validate_loaded(nd_ctx *c) {
   return ND_OK;
 }
 
+// (2,4): probe length of the triangle of each W entry = its shortest W list
+__global__ void k_w24_len(uint64_t nw, const uint32_t *__restrict__ wt,
+                          const uint32_t *__restrict__ te, const uint64_t *__restrict__ wp,
+                          uint32_t *__restrict__ len3) {
+  for (uint64_t p = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; p < nw;
+       p += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t t = wt[p];
+    uint64_t mn = ~0ull;
+    for (int j = 0; j < 3; j++) {
+      const uint32_t e = te[3 * t + j];
+      const uint64_t len = wp[e + 1] - wp[e];
+      mn = len < mn ? len : mn;
+    }
+    len3[p] = (uint32_t)mn;
+  }
+}
+
+// an edge's probe range must stay below 2^32 entries (32-bit work items)
+__global__ void k_w24_check(uint64_t m, const uint64_t *__restrict__ wp,
+                            const uint64_t *__restrict__ wg, uint32_t *status) {
+  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < m;
+       e += (uint64_t)gridDim.x * blockDim.x)
+    if (wg[wp[e + 1]] - wg[wp[e]] >= 0xFFFFFFFFull) atomicOr(status, ND_DERR_OVERFLOW);
+}
+
 static uint32_t coop_blocks(nd_ctx *c, const void *kernel, uint32_t block, uint32_t want) {
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess ||
@@ -585,7 +610,9 @@ nd_status nd_stage_prep(nd_ctx *c, GraphView *gv) {
   gv->wt = nullptr;
   gv->te = nullptr;
 
-  if (c->r == 3 && m) {
+  const bool tri_tables = c->r == 3 || (c->r == 2 && c->s == 4);
+  gv->wg = nullptr;
+  if (tri_tables && m) {
     uint32_t *sup = (uint32_t *)nd_buf(c, B_SUP, m * 4, &st);
     if (!sup) return st;
     uint32_t *upc = (uint32_t *)nd_buf(c, B_UPC, m * 4, &st);
@@ -603,7 +630,7 @@ nd_status nd_stage_prep(nd_ctx *c, GraphView *gv) {
     if (st != ND_OK) return st;
     if (ntri >= 0xFFFFFFFFull)
       return nd_fail(c, ND_E_OVERFLOW, "more than 2^32-2 triangles: 32-bit triangle ids overflow");
-    c->n_r = ntri;
+    c->n_r = c->r == 3 ? ntri : m;
     uint32_t *wc = (uint32_t *)nd_buf(c, B_WC, std::max<uint64_t>(nw, 1) * 4, &st);
     if (!wc) return st;
     uint32_t *wt = (uint32_t *)nd_buf(c, B_WT, std::max<uint64_t>(nw, 1) * 4, &st);
@@ -620,6 +647,24 @@ nd_status nd_stage_prep(nd_ctx *c, GraphView *gv) {
     gv->wc = wc;
     gv->wt = wt;
     gv->te = te;
+    if (c->r == 2) {
+      // (2,4): probe length of every W entry's triangle, summed over all
+      // entries, so a peeled edge can hand out the candidate 4th vertices of
+      // all its triangles as one flat range
+      uint32_t *len3 = (uint32_t *)nd_buf(c, B_W24L, std::max<uint64_t>(nw, 1) * 4, &st);
+      if (!len3) return st;
+      uint64_t *wg = (uint64_t *)nd_buf(c, B_WG, (nw + 1) * 8, &st);
+      if (!wg) return st;
+      if (nw)
+        hipLaunchKernelGGL(k_w24_len, dim3(nd_grid(nw, 256, 65536)), dim3(256), 0, c->stream, nw,
+                           wt, te, wp, len3);
+      uint64_t total = 0;
+      st = nd_exclusive_scan_u32_to_u64(c, len3, wg, nw, &total);
+      if (st != ND_OK) return st;
+      hipLaunchKernelGGL(k_w24_check, dim3(nd_grid(m, 256, 16384)), dim3(256), 0, c->stream, m,
+                         wp, wg, &sc->status);
+      gv->wg = wg;
+    }
   } else if (c->r == 3) {
     c->n_r = 0;
   } else if (c->r == 2) {

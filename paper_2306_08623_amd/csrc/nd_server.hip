@@ -44,9 +44,6 @@ struct Request {
   uint64_t *d_parent = nullptr;
 };
 
-bool supported(uint32_t r, uint32_t s) {
-  return (r == 1 && s == 2) || (r == 2 && s == 3) || (r == 3 && s == 4);
-}
 
 // workspace / result bytes of one graph (see nucleus.h); host CSR
 void estimate(uint32_t n, uint64_t nnz, const uint64_t *rp, const uint32_t *col, uint32_t r,
@@ -70,6 +67,7 @@ void estimate(uint32_t n, uint64_t nnz, const uint64_t *rp, const uint32_t *col,
   const uint64_t n_r = r == 1 ? n : (r == 2 ? m : tri);
   uint64_t w = 56ull * (n + 1) + 32ull * m + (150ull + 8ull * r) * n_r + 64;
   if (s >= 3) w += 24ull * (m + 1) + 36ull * tri;
+  if (r == 2 && s == 4) w += 40ull * tri;   // probe lengths + their running sums
   if (ws) *ws = w;
   if (res) *res = n_r * (4ull * r + 28ull) + 256;
 }
@@ -386,7 +384,7 @@ nd_status nd_server_submit(nd_server *S, const nd_graph_desc *d, nd_mem where,
                            uint64_t *ticket) {
   if (!S || !d || !ticket) return ND_E_INVALID_ARG;
   if (d->r < 1 || d->s <= d->r) return srv_fail(S, ND_E_INVALID_ARG, "need 1 <= r < s");
-  if (!supported(d->r, d->s)) return srv_fail(S, ND_E_UNSUPPORTED, "this (r,s) pair is not built");
+  if (!nd_rs_supported(d->r, d->s)) return srv_fail(S, ND_E_UNSUPPORTED, "this (r,s) pair is not built");
   if (!d->row_ptr || (d->nnz && !d->col)) return srv_fail(S, ND_E_INVALID_ARG, "NULL CSR");
   if (where != ND_MEM_HOST && where != ND_MEM_DEVICE)
     return srv_fail(S, ND_E_INVALID_ARG, "bad memory kind");

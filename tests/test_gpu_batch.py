@@ -46,6 +46,9 @@ def _degenerate():
         (I.cycle(10), 2, 3),
         (I.star(9), 1, 2),
         (I.complete(2), 3, 4),
+        (I.complete(7), 2, 4),
+        (I.batch_graph(0)[0], 2, 4),
+        (I.batch_graph(3)[0], 2, 4),
     ]
 
 
@@ -128,7 +131,7 @@ def test_batch_errors(ctx):
         ctx.decompose_batch([(ok, 2, 3), (bad, 2, 3)])
     assert e.value.code == nucleus.ND_E_BAD_GRAPH
     with pytest.raises(nucleus.NucleusError) as e:
-        ctx.decompose_batch([(ok, 2, 4)])
+        ctx.decompose_batch([(ok, 1, 3)])
     assert e.value.code == nucleus.ND_E_UNSUPPORTED
     with pytest.raises(nucleus.NucleusError) as e:
         ctx.decompose_batch([(ok, 3, 3)])
