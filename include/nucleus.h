@@ -73,7 +73,13 @@ typedef struct nd_options {
   uint32_t peel_blocks;   /* workgroups of the persistent peel launch; 0=auto */
   uint32_t work_chunk;    /* probe elements per lane task (>=1); 0 = auto     */
   uint64_t watchdog;      /* max peel rounds before ND_E_WATCHDOG; 0 = auto   */
+  uint32_t flags;         /* ND_FLAG_* bits                                   */
 } nd_options;
+
+/* nd_options.flags: print a line to stderr when a pipeline phase ends, and
+ * every 10 s of a running peel launch its round and level (read from pinned
+ * host memory the kernel updates), for runs that take minutes. */
+#define ND_FLAG_PROGRESS 1u
 
 /* Per-decomposition statistics. Counters are totals over the whole run. */
 typedef struct nd_info {

@@ -2,6 +2,11 @@
 // workspace, the decomposition pipeline and the result getters.
 #include "nd_internal.h"
 
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <thread>
+
 #include <algorithm>
 #include <cstring>
 #include <new>
@@ -71,6 +76,37 @@ nd_status nd_coop_launch(nd_ctx *c, const void *kern, dim3 grid, dim3 block, voi
   return st;
 }
 
+void nd_report(nd_ctx *c, const char *fmt, ...) {
+  if (!(c->flags & ND_FLAG_PROGRESS)) return;
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  std::fprintf(stderr, "[nd] %s\n", buf);
+  std::fflush(stderr);
+}
+
+void nd_report_while_running(nd_ctx *c, const char *phase, const uint32_t *progress) {
+  const auto t0 = std::chrono::steady_clock::now();
+  auto last = t0;
+  for (;;) {
+    const hipError_t q = hipStreamQuery(c->stream);
+    if (q != hipErrorNotReady) {
+      if (q != hipSuccess) (void)hipGetLastError();   // reported by the next sync
+      return;
+    }
+    std::this_thread::sleep_for(std::chrono::milliseconds(50));
+    const auto now = std::chrono::steady_clock::now();
+    if (now - last >= std::chrono::seconds(10)) {
+      last = now;
+      const volatile uint32_t *p = progress;
+      nd_report(c, "%s running %.0f s: round %u, level %u, frontier %u", phase,
+                std::chrono::duration<double>(now - t0).count(), p[0], p[1], p[2]);
+    }
+  }
+}
+
 static nd_status set_dev(nd_ctx *c) {
   return nd_hip(c, hipSetDevice(c->device), "hipSetDevice");
 }
@@ -119,6 +155,7 @@ nd_status nd_create(nd_ctx **out, const nd_options *opt) {
     c->peel_blocks = opt->peel_blocks;
     c->work_chunk = opt->work_chunk;
     c->watchdog = opt->watchdog;
+    c->flags = opt->flags;
   }
   g_create_error.clear();
   int ndev = 0;
@@ -144,6 +181,14 @@ nd_status nd_create(nd_ctx **out, const nd_options *opt) {
       !coop)
     return create_fail(c, ND_E_UNSUPPORTED, "the device does not support cooperative launches");
   c->bufs.resize(B_COUNT);
+  if (c->flags & ND_FLAG_PROGRESS) {
+    if (hipHostMalloc((void **)&c->progress, 16, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      c->progress = nullptr;
+      return create_fail(c, ND_E_OOM, "pinned progress words");
+    }
+    memset(c->progress, 0, 16);
+  }
   c->events_ok = true;
   for (int i = 0; i < 10; i++)
     if (hipEventCreate(&c->ev[i]) != hipSuccess) c->events_ok = false;
@@ -165,6 +210,7 @@ void nd_destroy(nd_ctx *c) {
     if (b.p) (void)hipFree(b.p);
   for (int i = 0; i < 10; i++)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  if (c->progress) (void)hipHostFree(c->progress);
   delete c;
 }
 
@@ -257,18 +303,23 @@ nd_status nd_run_pipeline(nd_ctx *c) {
   memset(&gv, 0, sizeof(gv));
   if ((st = nd_stage_prep(c, &gv)) != ND_OK) return st;
   if (c->events_ok) (void)hipEventRecord(c->ev[1], c->stream);
+  nd_report(c, "prep queued: n=%u m=%llu (r,s)=(%u,%u) n_r=%llu", c->n,
+            (unsigned long long)c->m, c->r, c->s, (unsigned long long)c->n_r);
   if ((st = nd_stage_count(c, gv)) != ND_OK) return st;
   if (c->events_ok) (void)hipEventRecord(c->ev[2], c->stream);
   DevScalars hs;
   if ((st = check_device_status(c, &hs)) != ND_OK) return st;
   c->info.n_s = hs.n_s;
   c->info.max_outdeg = hs.max_outdeg;
+  nd_report(c, "count done: n_s=%llu", (unsigned long long)hs.n_s);
   if ((st = nd_stage_peel(c, gv)) != ND_OK) return st;
   if (c->events_ok) (void)hipEventRecord(c->ev[3], c->stream);
   if ((st = check_device_status(c, &hs)) != ND_OK) return st;
+  nd_report(c, "peel done: %u rounds, k=%u", hs.rounds, hs.k);
   if ((st = nd_stage_tree(c, gv)) != ND_OK) return st;
   if (c->events_ok) (void)hipEventRecord(c->ev[4], c->stream);
   if ((st = check_device_status(c, &hs)) != ND_OK) return st;
+  nd_report(c, "tree done: %llu nodes", (unsigned long long)c->n_int);
   c->gv = gv;
   nd_info &I = c->info;
   I.n = c->n;

@@ -196,6 +196,8 @@ struct nd_ctx {
   uint32_t peel_blocks = 0;
   uint32_t work_chunk = 0;
   uint64_t watchdog = 0;
+  uint32_t flags = 0;          // ND_FLAG_*
+  uint32_t *progress = nullptr;   // pinned host words the peel kernel updates
   int cu_count = 0;
   std::string last_error;
 
@@ -295,6 +297,11 @@ nd_status nd_batch_plan(uint32_t G, const nd_graph_desc *graphs, nd_mem where,
 nd_status nd_batch_execute(nd_ctx *c, BatchState *bs, const nd_graph_desc *graphs,
                            nd_graph_result *results);
 void nd_batch_state_free(BatchState *bs);
+
+// progress reports (ND_FLAG_PROGRESS): a finished phase, and the peel's
+// round / level while its kernel runs (nd_api.hip)
+void nd_report(nd_ctx *c, const char *fmt, ...);
+void nd_report_while_running(nd_ctx *c, const char *phase, const uint32_t *progress);
 
 // the whole decomposition of the graph held in the context (nd_api.hip)
 nd_status nd_run_pipeline(nd_ctx *c);

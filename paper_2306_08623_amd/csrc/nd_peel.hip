@@ -61,6 +61,7 @@ struct PeelArgs {
   DevScalars *sc;
   uint32_t nblocks;
   uint32_t max_rounds;
+  uint32_t *progress;   // host-visible [round, level, frontier], or null
 };
 
 // ---------------------------------------------------------------------------
@@ -571,6 +572,14 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
       f = ld_acq32(&sc->fsize[t & 1]);
     }
 
+    if (a.progress && gtid == 0) {
+      // progress for a host that reports long runs (system-scope stores into
+      // pinned host memory; read by the host while the kernel runs)
+      __hip_atomic_store(&a.progress[0], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(&a.progress[1], k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(&a.progress[2], f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+
     // ---- mark: core number and peel round; per-segment work prefix sums
     const uint64_t seg = (f + nb - 1) / nb;
     const uint64_t sbeg = min64((uint64_t)blockIdx.x * seg, f);
@@ -770,9 +779,11 @@ nd_status launch_peel(nd_ctx *c, PeelArgs &pa) {
   uint32_t nb = (uint32_t)std::max<uint64_t>(1, std::min(want, cap));
   pa.nblocks = nb;
   void *args[] = {&pa};
-  return nd_coop_launch(c, kern, dim3(nb), dim3(kPeelBlock), args,
-                        c->events_ok ? c->ev[5] : nullptr, c->events_ok ? c->ev[6] : nullptr,
-                        "peel launch");
+  nd_status st = nd_coop_launch(c, kern, dim3(nb), dim3(kPeelBlock), args,
+                                c->events_ok ? c->ev[5] : nullptr,
+                                c->events_ok ? c->ev[6] : nullptr, "peel launch");
+  if (st == ND_OK && pa.progress) nd_report_while_running(c, "peel", pa.progress);
+  return st;
 }
 
 }  // namespace
@@ -810,6 +821,8 @@ nd_status nd_stage_peel(nd_ctx *c, const GraphView &g) {
       return st;
   }
   pa.sc = sc;
+  pa.progress = c->progress;
+  if (pa.progress) memset(pa.progress, 0, 4 * sizeof(uint32_t));
   uint64_t wd = c->watchdog ? c->watchdog : nr + 2;
   pa.max_rounds = (uint32_t)std::min<uint64_t>(wd, 0xFFFFFFF0ull);
 

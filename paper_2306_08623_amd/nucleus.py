@@ -38,6 +38,8 @@ ND_E_CANCELLED = 9
 ND_MEM_HOST = 0
 ND_MEM_DEVICE = 1
 
+ND_FLAG_PROGRESS = 1
+
 NONE64 = np.uint64(0xFFFFFFFFFFFFFFFF)
 
 # Every function the C ABI exports (kept in sync with include/nucleus.h).
@@ -61,6 +63,7 @@ class Options(C.Structure):
         ("peel_blocks", C.c_uint32),
         ("work_chunk", C.c_uint32),
         ("watchdog", C.c_uint64),
+        ("flags", C.c_uint32),
     ]
 
 
@@ -264,7 +267,7 @@ class Context:
 
     def __init__(self, device: int = 0, stream=None, validate: bool = True, mem_limit: int = 0,
                  peel_blocks: int = 0, work_chunk: int = 0, watchdog: int = 0,
-                 use_torch_stream: bool = True):
+                 use_torch_stream: bool = True, progress: bool = False):
         self.lib = load_library()
         opt = Options()
         opt.device = device
@@ -276,6 +279,7 @@ class Context:
         opt.peel_blocks = peel_blocks
         opt.work_chunk = work_chunk
         opt.watchdog = watchdog
+        opt.flags = ND_FLAG_PROGRESS if progress else 0
         h = C.c_void_p()
         st = self.lib.nd_create(C.byref(h), C.byref(opt))
         if st != ND_OK:

@@ -127,3 +127,15 @@ def test_error_paths(ctx):
         assert e.value.code == nucleus.ND_E_OOM
     # the context is still usable after errors
     check(ctx, I.complete(6), 2, 3, "after-errors")
+
+
+def test_progress_reports(capfd):
+    """ND_FLAG_PROGRESS prints the end of every phase to stderr."""
+    from paper_2306_08623_amd import nucleus
+    g = I.workload_er2k()
+    with nucleus.Context(device=0, progress=True) as c2:
+        res = c2.decompose(g, 3, 4)
+    err = capfd.readouterr().err
+    for tag in ("prep queued", "count done", "peel done", "tree done"):
+        assert f"[nd] {tag}" in err, err
+    assert f"n_s={res.info['n_s']}" in err
