@@ -80,6 +80,16 @@ typedef struct nd_options {
  * every 10 s of a running peel launch its round and level (read from pinned
  * host memory the kernel updates), for runs that take minutes. */
 #define ND_FLAG_PROGRESS 1u
+/* How the hierarchy is built (the result is the same canonical tree):
+ *  EL: during the peel, by Algorithm 5's link-efficient (Section 7.3);
+ *  TE: after a peel without linking, level by level from the largest core
+ *      number down (the paper's two-pass alternative, Section 7.4), with a
+ *      union-find of partial trees that keeps each step independent of the
+ *      depth of the hierarchy.
+ * Neither flag: TE for (2,4), whose core numbers span thousands of levels
+ * (Algorithm 5's link chains grow with them), EL for the other pairs. */
+#define ND_FLAG_HIER_EL 2u
+#define ND_FLAG_HIER_TE 4u
 
 /* Per-decomposition statistics. Counters are totals over the whole run. */
 typedef struct nd_info {
@@ -92,7 +102,8 @@ typedef struct nd_info {
   uint64_t n_int;         /* internal nodes of the canonical tree             */
   uint64_t visits;        /* (r-clique, s-clique) pairs traversed while peeling */
   uint64_t decrements;    /* count decrements                                 */
-  uint64_t links;         /* link steps (Algorithm 5 calls, cascades included) */
+  uint64_t links;         /* EL: link steps (Algorithm 5 calls, cascades
+                             included); TE: pairs handled by the hierarchy    */
   uint64_t link_calls;    /* top-level link calls issued (after skipping pairs
                              of roots already linked)                         */
   uint64_t unites;        /* successful union-find unions                     */
@@ -106,6 +117,9 @@ typedef struct nd_info {
   float ms_count_kernel;  /* device time of the s-clique counting kernel      */
   float ms_peel_kernel;   /* device time of the persistent peel+link kernel   */
   uint64_t device_bytes;  /* workspace bytes held by the context              */
+  uint32_t hier_te;       /* 1 if the hierarchy was built by the TE pass      */
+  float ms_hier;          /* TE: device time of level sort + hierarchy kernel */
+  uint64_t hier_visits;   /* TE: s-cliques met by the hierarchy kernel        */
 } nd_info;
 
 /* Create a context on opt->device (opt may be NULL: device 0, null stream,

@@ -336,6 +336,7 @@ nd_status nd_run_pipeline(nd_ctx *c) {
   I.link_calls = hs.link_calls;
   I.unites = hs.unites;
   I.bucket_scans = hs.bucket_scans;
+  I.hier_visits = hs.hier_visits;
   I.orient_rounds = hs.orient_round;
   I.device_bytes = c->bytes_held;
   if (c->events_ok) {
@@ -348,6 +349,8 @@ nd_status nd_run_pipeline(nd_ctx *c) {
       I.ms_peel_kernel = ms;
     if (c->s > 2 && c->m && hipEventElapsedTime(&ms, c->ev[7], c->ev[8]) == hipSuccess)
       I.ms_count_kernel = ms;
+    if (I.hier_te && c->n_r && hipEventElapsedTime(&ms, c->ev[6], c->ev[9]) == hipSuccess)
+      I.ms_hier = ms;
     (void)hipGetLastError();
   }
   c->decomposed = true;

@@ -409,6 +409,9 @@ static void add_info(nd_info &T, const nd_info &I) {
   T.ms_tree += I.ms_tree;
   T.ms_count_kernel += I.ms_count_kernel;
   T.ms_peel_kernel += I.ms_peel_kernel;
+  T.hier_te |= I.hier_te;
+  T.ms_hier += I.ms_hier;
+  T.hier_visits += I.hier_visits;
 }
 
 // Host half of a batch: checks, grouping by (r,s) and, for host inputs, the

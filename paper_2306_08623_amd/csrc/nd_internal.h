@@ -45,14 +45,28 @@ struct GraphView {
   const uint32_t *wc;        // [3 n_tri] W entries (third vertex), ascending per edge
   const uint32_t *wt;        // [3 n_tri] triangle id of each W entry
   const uint32_t *te;        // [3 n_tri] (e_ab, e_ac, e_bc) of triangle (a<b<c)
-  // (2,4) only: running sum over all W entries of the probe length of the
-  // entry's triangle (shortest W list among its three edges); [3 n_tri + 1]
+  // (2,4) only, per W entry (edge e, third vertex w, triangle t): the probed
+  // list part, (list << 30 | start offset) with list 0 = W(e), 1/2 = W of
+  // t's other edges in te order, holding t's candidates x > w; and the
+  // running sum of the parts' lengths over all entries ([3 n_tri + 1])
+  const uint32_t *wsel;
   const uint64_t *wg;
 };
 
 // ---------------------------------------------------------------------------
 // Device helpers
 // ---------------------------------------------------------------------------
+
+// first index x in [lo, hi) with a[x] > v (a ascending), hi if none
+__device__ __forceinline__ uint64_t upper_bound_u32(const uint32_t *a, uint64_t lo, uint64_t hi,
+                                                    uint32_t v) {
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi) >> 1;
+    if (a[mid] <= v) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
 
 // Coherent (agent-scope) relaxed atomics. Plain loads may hit a stale line in
 // another XCD's L2; these go to the coherence point.
@@ -240,9 +254,14 @@ enum BufId : int {
   B_SCAL, B_TMP64, B_TMP32A, B_TMP32B, B_TMP32C, B_TMP32D,
   B_SORTK0, B_SORTK1, B_SORTV0, B_SORTV1, B_HIST,
   B_PARENT, B_LEVEL, B_RCL, B_GCACHE, B_ACNT, B_NODEML, B_SORTOFF,
-  B_BATCHDESC, B_WG, B_W24L,
+  B_BATCHDESC, B_WG, B_W24L, B_LHIST, B_LOFF,
   B_COUNT
 };
+
+// hierarchy construction: Algorithm 5 during the peel ("EL"), or the
+// two-pass descending-core construction after it ("TE"); by default TE for
+// (2,4), whose core numbers span thousands of levels, EL otherwise
+inline bool nd_use_te(const nd_ctx *c);
 
 // the (r,s) pairs whose peel is built; index of a pair's batch slots
 inline bool nd_rs_supported(uint32_t r, uint32_t s) {
@@ -264,6 +283,7 @@ struct DevScalars {
   uint64_t visits, decrements, links, unites;
   uint64_t bucket_scans;
   uint64_t link_calls;     // link calls issued after the redundancy filter
+  uint64_t hier_visits;    // s-cliques found by the descending-core hierarchy pass
   uint32_t status;         // ND_DERR_* bits
   uint32_t k;              // final level reached
   uint32_t rounds;         // peel rounds executed
@@ -327,4 +347,10 @@ inline uint32_t nd_grid(uint64_t work, uint32_t block, uint32_t cap = 1u << 20) 
   if (g < 1) g = 1;
   if (g > cap) g = cap;
   return (uint32_t)g;
+}
+
+inline bool nd_use_te(const nd_ctx *c) {
+  if (c->flags & ND_FLAG_HIER_TE) return true;
+  if (c->flags & ND_FLAG_HIER_EL) return false;
+  return c->r == 2 && c->s == 4;
 }

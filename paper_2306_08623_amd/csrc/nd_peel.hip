@@ -311,12 +311,12 @@ struct Shape<3, 4> {
 
 // (2,4): R = edge e = {u, v}. A 4-clique {u, v, w, x} containing e is a
 // triangle t = {u, v, w} on e (an entry of W(e)) extended by a common
-// neighbour x of t; probe entries are, for every triangle t of e in W(e)
-// order, the entries of t's shortest W list, as one flat range (wg holds the
-// running sums). Each 4-clique is taken from the triangle with the smaller
-// of its two extra vertices (x > w), so it is met once. The other five edges
-// are {u,w}, {v,w} (from t), {u,x}, {v,x} (from triangle {u,v,x}, x's entry
-// in W(e)) and {w,x} (from triangle {u,w,x} or {v,w,x}).
+// neighbour x of t, taken from the triangle with the smaller extra vertex
+// (w < x) so that it is met once. Probe entries are, for every triangle t of
+// e in W(e) order, the entries above w of t's shortest W list part (chosen
+// in prep: wsel), as one flat range (wg holds the running sums). The other
+// five edges are {u,w}, {v,w} (from t), {u,x}, {v,x} (from triangle {u,v,x},
+// x's entry in W(e)) and {w,x} (from triangle {u,w,x}, x's entry in W(x1)).
 template <>
 struct Shape<2, 4> {
   static constexpr int kOthers = 5;
@@ -334,57 +334,54 @@ struct Shape<2, 4> {
       else hi = mid;
     }
     const uint64_t pt = lo;
-    const uint32_t w = g.wc[pt];
-    const uint32_t t = g.wt[pt];
     const uint64_t j = target - g.wg[pt];
-    // t's edges: R and the two edges to w
-    uint32_t ea = g.te[3ull * t], eb = g.te[3ull * t + 1], ec = g.te[3ull * t + 2];
-    uint32_t x1, x2;   // the edges of t other than R
-    if (ea == R) { x1 = eb; x2 = ec; }
-    else if (eb == R) { x1 = ea; x2 = ec; }
-    else { x1 = ea; x2 = eb; }
-    // probe t's shortest list (R's own list W(e) or one of x1, x2)
-    const uint64_t sR = f - b, s1 = g.wp[x1 + 1] - g.wp[x1], s2 = g.wp[x2 + 1] - g.wp[x2];
+    const uint32_t t = g.wt[pt];
+    const uint32_t sl = g.wsel[pt];
+    // t's edges other than R, in te order
+    uint32_t xs[2], nx = 0;
+    for (int q = 0; q < 3; q++) {
+      const uint32_t z = g.te[3ull * t + q];
+      if (z != R && nx < 2) xs[nx++] = z;
+    }
+    const uint32_t x1 = xs[0], x2 = xs[1];
+    const uint32_t which = sl >> 30, off = sl & 0x3FFFFFFFu;
     uint64_t pR, p1;
-    uint32_t x;
-    if (sR <= s1 && sR <= s2) {
-      pR = b + j;
-      x = g.wc[pR];
-      if (x <= w) return false;
+    if (which == 0) {
+      pR = b + off + j;
+      const uint32_t x = g.wc[pR];
       p1 = find_u32<uint64_t>(g.wc, g.wp[x1], g.wp[x1 + 1], x);
       if (p1 == g.wp[x1 + 1]) return false;
       const uint64_t p2 = find_u32<uint64_t>(g.wc, g.wp[x2], g.wp[x2 + 1], x);
       if (p2 == g.wp[x2 + 1]) return false;
     } else {
-      const uint32_t ep = s1 <= s2 ? x1 : x2, eo = s1 <= s2 ? x2 : x1;
-      const uint64_t pp = g.wp[ep] + j;
-      x = g.wc[pp];
-      if (x <= w) return false;
+      const uint32_t ep = which == 1 ? x1 : x2, eo = which == 1 ? x2 : x1;
+      const uint64_t pp = g.wp[ep] + off + j;
+      const uint32_t x = g.wc[pp];
       const uint64_t po = find_u32<uint64_t>(g.wc, g.wp[eo], g.wp[eo + 1], x);
       if (po == g.wp[eo + 1]) return false;
       pR = find_u32<uint64_t>(g.wc, b, f, x);
       if (pR == f) return false;
-      p1 = ep == x1 ? pp : po;
+      p1 = which == 1 ? pp : po;
     }
     // triangle {u,v,x}: its edges other than R are {u,x}, {v,x}
     const uint32_t tx = g.wt[pR];
-    uint32_t ya = g.te[3ull * tx], yb = g.te[3ull * tx + 1], yc = g.te[3ull * tx + 2];
-    uint32_t y1, y2;
-    if (ya == R) { y1 = yb; y2 = yc; }
-    else if (yb == R) { y1 = ya; y2 = yc; }
-    else { y1 = ya; y2 = yb; }
-    // triangle on x1 with x: its edges are x1, one of {y1, y2}, and {w,x}
+    uint32_t ys[2], ny = 0;
+    for (int q = 0; q < 3; q++) {
+      const uint32_t z = g.te[3ull * tx + q];
+      if (z != R && ny < 2) ys[ny++] = z;
+    }
+    // triangle on x1 with x: its edges are x1, one of ys, and {w,x}
     const uint32_t tw = g.wt[p1];
     uint32_t wx = ND_NONE;
     for (int q = 0; q < 3; q++) {
       const uint32_t z = g.te[3ull * tw + q];
-      if (z != x1 && z != y1 && z != y2) wx = z;
+      if (z != x1 && z != ys[0] && z != ys[1]) wx = z;
     }
     if (wx == ND_NONE) return false;   // unreachable for consistent tables
     o[0] = x1;
     o[1] = x2;
-    o[2] = y1;
-    o[3] = y2;
+    o[2] = ys[0];
+    o[3] = ys[1];
     o[4] = wx;
     return true;
   }
@@ -447,7 +444,7 @@ __device__ __forceinline__ uint32_t key_root(const uint32_t *uf, uint32_t x) {
 // the persistent kernel
 // ---------------------------------------------------------------------------
 
-template <int R_, int S_>
+template <int R_, int S_, bool kLink>
 __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
   using Sh = Shape<R_, S_>;
   constexpr int NO = Sh::kOthers;
@@ -695,7 +692,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
           uint32_t qroot = ND_NONE;   // cache key of R's set, formed on first use
 #pragma unroll
           for (int j = 0; j < NO; j++) {
-            if (rr[j] < t || (rr[j] == t && R < others[j])) {
+            if (kLink && (rr[j] < t || (rr[j] == t && R < others[j]))) {
               if (qroot == ND_NONE) qroot = key_root(a.uf, R);
               const uint32_t x = key_root(a.uf, others[j]);
               if (x == qroot || lcache_hit(s_lcache, x, qroot)) continue;
@@ -723,7 +720,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
 
     // ---- drain spilled link pairs (rare): repeat until the queue is empty
     bool ok = true;
-    for (;;) {
+    for (; kLink;) {
       const uint32_t h = ld_acq32(&sc->linkq_head);
       const uint32_t tl = ld_acq32(&sc->linkq_tail);
       if (h == tl) break;
@@ -760,29 +757,288 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Hierarchy by descending core number (the two-pass construction, "TE"):
+// after a peel without linking, the same union-find uf (same-core
+// components) and nearest-lower-core table L that Algorithm 5 builds are
+// built level by level, c = k down to 1. When level c starts, every part of
+// the hierarchy above c is final and forms trees; a second union-find (tuf)
+// groups r-cliques by tree and remembers each tree's lowest component
+// (bottom). An r-clique R of core c that shares an s-clique with R' (core
+// >= c) either joins R''s component (same core), or hangs R''s tree below
+// R's component: L[bottom] = R, set once by CAS; a later r-clique of core c
+// that reaches the same tree finds L taken and joins the component that took
+// it. Each pair costs a few union-find operations, independent of the depth
+// of the hierarchy; Algorithm 5 instead walks L chains level by level, which
+// is slow when core numbers span thousands of levels.
+// ---------------------------------------------------------------------------
+
+struct HierArgs {
+  GraphView g;
+  uint64_t n_r;
+  const uint32_t *nd;      // core numbers
+  const uint32_t *ord;     // r-cliques by core number, descending
+  const uint64_t *loff;    // [k + 2]: core c occupies ord[loff[k - c], loff[k - c + 1])
+  uint32_t *uf, *L, *tuf, *bottom;
+  uint64_t *wscan;
+  uint64_t *btot;
+  DevScalars *sc;
+  uint32_t nblocks;
+  uint32_t k;
+  uint32_t *progress;
+};
+
+__device__ __forceinline__ void hier_pair(const HierArgs &a, uint32_t R, uint32_t R2, uint32_t c,
+                                          uint64_t &unites) {
+  const uint32_t n2 = a.nd[R2];
+  if (n2 == c) {   // same core: one component, one tree
+    unites += uf_unite(a.uf, R, R2) != ND_NONE;
+    uf_unite(a.tuf, R, R2);
+    return;
+  }
+  const uint32_t T = uf_find(a.tuf, R2);
+  const uint32_t B = ld_acq32(&a.bottom[T]);
+  if (a.nd[B] == c) {   // R2's tree already hangs below a core-c component
+    unites += uf_unite(a.uf, B, R) != ND_NONE;
+    uf_unite(a.tuf, T, R);
+    return;
+  }
+  // R2's tree still ends at a component of a higher core: hang it below R
+  const uint32_t Bs = uf_find(a.uf, B);   // final: that core is finished
+  const uint32_t old = atomicCAS(&a.L[Bs], ND_NONE, R);
+  if (old == ND_NONE) {
+    uf_unite(a.tuf, T, R);
+    const uint32_t w = uf_find(a.tuf, R);
+    __hip_atomic_store(&a.bottom[w], R, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {   // taken at this level by the component of `old`
+    unites += uf_unite(a.uf, old, R) != ND_NONE;
+    uf_unite(a.tuf, T, R);
+  }
+}
+
+template <int R_, int S_>
+__global__ void __launch_bounds__(kPeelBlock) k_hier(HierArgs a) {
+  using Sh = Shape<R_, S_>;
+  constexpr int NO = Sh::kOthers;
+  __shared__ uint64_t s_boff[kMaxPeelBlocks + 1];
+  __shared__ uint64_t s_red64[kPeelBlock / 64];
+
+  DevScalars *sc = a.sc;
+  const GraphView &g = a.g;
+  const uint32_t nb = a.nblocks;
+  const uint32_t lane = lane_id();
+  const uint32_t wv = threadIdx.x / 64;
+  const uint64_t gtid = blockIdx.x * (uint64_t)kPeelBlock + threadIdx.x;
+  const uint64_t nthreads = (uint64_t)nb * kPeelBlock;
+  uint64_t visits = 0, pairs = 0, unites = 0;
+
+  for (uint32_t c = a.k; c >= 1; c--) {
+    const uint64_t fb = a.loff[a.k - c], fe = a.loff[a.k - c + 1];
+    const uint64_t f = fe - fb;
+    if (f == 0) continue;   // the same decision in every workgroup
+    const uint32_t *F = a.ord + fb;
+    if (a.progress && gtid == 0) {
+      __hip_atomic_store(&a.progress[0], a.k - c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(&a.progress[1], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(&a.progress[2], (uint32_t)f, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    // per-segment inclusive prefix of the probe work of this level's r-cliques
+    const uint64_t seg = (f + nb - 1) / nb;
+    const uint64_t sbeg = min64((uint64_t)blockIdx.x * seg, f);
+    const uint64_t send = min64(sbeg + seg, f);
+    uint64_t run = 0;
+    for (uint64_t base = sbeg; base < send; base += kPeelBlock) {
+      const uint64_t i = base + threadIdx.x;
+      const uint32_t w = i < send ? Sh::len(g, F[i]) : 0;
+      const uint32_t incl = wave_incl_scan(w);
+      if (lane == 63) s_red64[wv] = incl;
+      __syncthreads();
+      uint64_t wpre = 0, btot = 0;
+      for (uint32_t x = 0; x < kPeelBlock / 64; x++) {
+        if (x < wv) wpre += s_red64[x];
+        btot += s_red64[x];
+      }
+      if (i < send) a.wscan[i] = run + wpre + incl;
+      run += btot;
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) a.btot[blockIdx.x] = run;
+    if (!grid_barrier(&sc->barrier, nb, &sc->status)) break;
+    {
+      const uint32_t per = (nb + kPeelBlock - 1) / kPeelBlock;
+      const uint32_t j0 = threadIdx.x * per;
+      uint64_t mine = 0;
+      for (uint32_t j = j0; j < j0 + per && j < nb; j++) mine += a.btot[j];
+      uint64_t incl = mine;
+      for (int d = 1; d < 64; d <<= 1) {
+        uint64_t y = __shfl_up(incl, d, 64);
+        if (lane >= (uint32_t)d) incl += y;
+      }
+      if (lane == 63) s_red64[wv] = incl;
+      __syncthreads();
+      uint64_t acc = incl - mine;
+      for (uint32_t x = 0; x < wv; x++) acc += s_red64[x];
+      for (uint32_t j = j0; j < j0 + per && j < nb; j++) {
+        s_boff[j] = acc;
+        acc += a.btot[j];
+      }
+      if (threadIdx.x == kPeelBlock - 1) s_boff[nb] = acc;
+      __syncthreads();
+    }
+    const uint64_t P = s_boff[nb];
+    for (uint64_t base = blockIdx.x * (uint64_t)kPeelBlock + wv * 64ull; base < P;
+         base += nthreads) {
+      const uint64_t p = base + lane;
+      if (p < P) {
+        uint32_t lo = 0, hi = nb;   // s_boff[lo] <= p < s_boff[hi]
+        while (hi - lo > 1) {
+          uint32_t mid = (lo + hi) >> 1;
+          if (s_boff[mid] <= p) lo = mid;
+          else hi = mid;
+        }
+        const uint64_t qoff = p - s_boff[lo];
+        const uint64_t b0 = min64((uint64_t)lo * seg, f);
+        const uint64_t b1 = min64(b0 + seg, f);
+        const uint64_t x0 = gallop_u64(a.wscan, b0, b1, qoff);
+        const uint32_t R = F[x0];
+        const uint64_t before = (x0 > b0) ? a.wscan[x0 - 1] : 0;
+        uint32_t others[NO];
+        if (Sh::visit(g, R, (uint32_t)(qoff - before), others)) {
+          visits++;
+#pragma unroll
+          for (int j = 0; j < NO; j++) {
+            if (a.nd[others[j]] >= c) {
+              pairs++;
+              hier_pair(a, R, others[j], c, unites);
+            }
+          }
+        }
+      }
+    }
+    if (!grid_barrier(&sc->barrier, nb, &sc->status)) break;
+  }
+  const uint64_t v = wave_sum64(visits), l = wave_sum64(pairs), u = wave_sum64(unites);
+  if (lane == 0) {
+    if (v) atomicAdd((unsigned long long *)&sc->hier_visits, (unsigned long long)v);
+    if (l) atomicAdd((unsigned long long *)&sc->links, (unsigned long long)l);
+    if (u) atomicAdd((unsigned long long *)&sc->unites, (unsigned long long)u);
+  }
+}
+
+// r-cliques by core number, descending (counting sort; order inside a level
+// is free)
+__global__ void k_level_hist(uint64_t n, const uint32_t *__restrict__ nd, uint32_t k,
+                             uint32_t *__restrict__ hist) {
+  for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n;
+       x += (uint64_t)gridDim.x * blockDim.x)
+    atomicAdd(&hist[k - nd[x]], 1u);
+}
+
+__global__ void k_level_scatter(uint64_t n, const uint32_t *__restrict__ nd, uint32_t k,
+                                const uint64_t *__restrict__ loff, uint32_t *__restrict__ fill,
+                                uint32_t *__restrict__ ord) {
+  for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n;
+       x += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t b = k - nd[x];
+    ord[loff[b] + atomicAdd(&fill[b], 1u)] = (uint32_t)x;
+  }
+}
+
 __global__ void k_iota(uint32_t *a, uint64_t n) {
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
        i += (uint64_t)gridDim.x * blockDim.x)
     a[i] = (uint32_t)i;
 }
 
-template <int R_, int S_>
-nd_status launch_peel(nd_ctx *c, PeelArgs &pa) {
-  const void *kern = (const void *)k_peel<R_, S_>;
+// persistent grid: as many workgroups as fit on the device at once
+template <typename K>
+uint32_t coop_grid(nd_ctx *c, K kern, uint32_t *nb) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kPeelBlock, 0) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, kPeelBlock, 0) !=
+          hipSuccess ||
       per_cu < 1)
-    return nd_fail(c, ND_E_DEVICE, "occupancy query failed for the peel kernel");
+    return 0;
   uint64_t cap = (uint64_t)per_cu * (uint64_t)c->cu_count;
   cap = std::min<uint64_t>(cap, kMaxPeelBlocks);
   uint64_t want = c->peel_blocks ? c->peel_blocks : cap;
-  uint32_t nb = (uint32_t)std::max<uint64_t>(1, std::min(want, cap));
+  *nb = (uint32_t)std::max<uint64_t>(1, std::min(want, cap));
+  return *nb;
+}
+
+template <int R_, int S_, bool kLink>
+nd_status launch_peel(nd_ctx *c, PeelArgs &pa) {
+  const void *kern = (const void *)k_peel<R_, S_, kLink>;
+  uint32_t nb = 0;
+  if (!coop_grid(c, k_peel<R_, S_, kLink>, &nb))
+    return nd_fail(c, ND_E_DEVICE, "occupancy query failed for the peel kernel");
   pa.nblocks = nb;
   void *args[] = {&pa};
   nd_status st = nd_coop_launch(c, kern, dim3(nb), dim3(kPeelBlock), args,
                                 c->events_ok ? c->ev[5] : nullptr,
                                 c->events_ok ? c->ev[6] : nullptr, "peel launch");
   if (st == ND_OK && pa.progress) nd_report_while_running(c, "peel", pa.progress);
+  return st;
+}
+
+// Two passes: the peel without linking, then k_hier over the core numbers.
+template <int R_, int S_>
+nd_status run_te(nd_ctx *c, PeelArgs &pa) {
+  nd_status st = launch_peel<R_, S_, false>(c, pa);
+  if (st != ND_OK) return st;
+  DevScalars *sc = pa.sc;
+  uint32_t hk[2] = {0, 0};
+  if ((st = nd_hip(c, hipMemcpyAsync(hk, &sc->status, 8, hipMemcpyDeviceToHost, c->stream),
+                   "peel result")) != ND_OK ||
+      (st = nd_hip(c, hipStreamSynchronize(c->stream), "peel result")) != ND_OK)
+    return st;
+  if (hk[0]) return ND_OK;   // device error: reported by the status check that follows
+  const uint32_t k = hk[1];
+  nd_report(c, "peel (no links) done: k=%u; hierarchy by descending core", k);
+  const uint64_t nr = pa.n_r;
+  HierArgs h{};
+  h.g = pa.g;
+  h.n_r = nr;
+  h.nd = pa.cnt;
+  h.uf = pa.uf;
+  h.L = pa.L;
+  h.ord = pa.F0;
+  h.tuf = pa.al0;
+  h.bottom = pa.al1;
+  h.wscan = pa.wscan;
+  h.btot = pa.btot;
+  h.sc = sc;
+  h.k = k;
+  h.progress = pa.progress;
+  uint32_t *hist = (uint32_t *)nd_buf(c, B_LHIST, (k + 2ull) * 4, &st);
+  if (!hist) return st;
+  uint64_t *loff = (uint64_t *)nd_buf(c, B_LOFF, (k + 2ull) * 8, &st);
+  if (!loff) return st;
+  h.loff = loff;
+  if ((st = nd_hip(c, hipMemsetAsync(hist, 0, (k + 2ull) * 4, c->stream), "level hist")) != ND_OK)
+    return st;
+  hipLaunchKernelGGL(k_level_hist, dim3(nd_grid(nr, 256, 16384)), dim3(256), 0, c->stream, nr,
+                     pa.cnt, k, hist);
+  uint64_t total = 0;
+  if ((st = nd_exclusive_scan_u32_to_u64(c, hist, loff, k + 1ull, &total)) != ND_OK) return st;
+  if ((st = nd_hip(c, hipMemsetAsync(hist, 0, (k + 2ull) * 4, c->stream), "level fill")) != ND_OK)
+    return st;
+  hipLaunchKernelGGL(k_level_scatter, dim3(nd_grid(nr, 256, 16384)), dim3(256), 0, c->stream, nr,
+                     pa.cnt, k, loff, hist, pa.F0);
+  hipLaunchKernelGGL(k_iota, dim3(nd_grid(nr, 256, 16384)), dim3(256), 0, c->stream, pa.al0, nr);
+  hipLaunchKernelGGL(k_iota, dim3(nd_grid(nr, 256, 16384)), dim3(256), 0, c->stream, pa.al1, nr);
+  if ((st = nd_hip(c, hipMemsetAsync(&sc->barrier, 0, 8, c->stream), "barrier")) != ND_OK)
+    return st;
+  if ((st = nd_hip(c, hipGetLastError(), "level sort")) != ND_OK) return st;
+  if (pa.progress) memset(pa.progress, 0, 4 * sizeof(uint32_t));
+  uint32_t nb = 0;
+  if (!coop_grid(c, k_hier<R_, S_>, &nb))
+    return nd_fail(c, ND_E_DEVICE, "occupancy query failed for the hierarchy kernel");
+  h.nblocks = nb;
+  void *args[] = {&h};
+  st = nd_coop_launch(c, (const void *)k_hier<R_, S_>, dim3(nb), dim3(kPeelBlock), args,
+                      nullptr, c->events_ok ? c->ev[9] : nullptr, "hierarchy launch");
+  if (st == ND_OK && h.progress) nd_report_while_running(c, "hierarchy", h.progress);
   return st;
 }
 
@@ -794,7 +1050,7 @@ nd_status nd_stage_peel(nd_ctx *c, const GraphView &g) {
   DevScalars *sc = (DevScalars *)c->bufs[B_SCAL].p;
   if (nr == 0) return ND_OK;
   if (nr >= 0xFFFFFFFFull) return nd_fail(c, ND_E_OVERFLOW, "r-clique ids exceed 32 bits");
-  PeelArgs pa;
+  PeelArgs pa{};
   pa.g = g;
   pa.n_r = nr;
   pa.cnt = (uint32_t *)c->bufs[B_CNT].p;
@@ -845,9 +1101,11 @@ nd_status nd_stage_peel(nd_ctx *c, const GraphView &g) {
   if ((st = nd_hip(c, hipStreamSynchronize(c->stream), "peel scalars sync")) != ND_OK) return st;
 
   const uint32_t r = c->r, s = c->s;
-  if (r == 1 && s == 2) return launch_peel<1, 2>(c, pa);
-  if (r == 2 && s == 3) return launch_peel<2, 3>(c, pa);
-  if (r == 3 && s == 4) return launch_peel<3, 4>(c, pa);
-  if (r == 2 && s == 4) return launch_peel<2, 4>(c, pa);
+  const bool te = nd_use_te(c);
+  c->info.hier_te = te ? 1 : 0;
+  if (r == 1 && s == 2) return te ? run_te<1, 2>(c, pa) : launch_peel<1, 2, true>(c, pa);
+  if (r == 2 && s == 3) return te ? run_te<2, 3>(c, pa) : launch_peel<2, 3, true>(c, pa);
+  if (r == 3 && s == 4) return te ? run_te<3, 4>(c, pa) : launch_peel<3, 4, true>(c, pa);
+  if (r == 2 && s == 4) return te ? run_te<2, 4>(c, pa) : launch_peel<2, 4, true>(c, pa);
   return nd_fail(c, ND_E_UNSUPPORTED, "peeling for this (r,s) is not built");
 }

@@ -470,20 +470,40 @@ nd_status nd_validate_loaded(nd_ctx *c) {
   return ND_OK;
 }
 
-// (2,4): probe length of the triangle of each W entry = its shortest W list
-__global__ void k_w24_len(uint64_t nw, const uint32_t *__restrict__ wt,
-                          const uint32_t *__restrict__ te, const uint64_t *__restrict__ wp,
-                          uint32_t *__restrict__ len3) {
-  for (uint64_t p = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; p < nw;
-       p += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t t = wt[p];
-    uint64_t mn = ~0ull;
-    for (int j = 0; j < 3; j++) {
-      const uint32_t e = te[3 * t + j];
-      const uint64_t len = wp[e + 1] - wp[e];
-      mn = len < mn ? len : mn;
+// (2,4): for each W entry (edge e = {u,v}, third vertex w, triangle t), the
+// candidates x > w of t's 4-cliques lie in the parts above w of W(e),
+// W(x1), W(x2) (x1, x2 = t's other edges, in te order); the shortest of the
+// three parts is probed. sel[p] = (list index << 30) | start offset of the
+// part inside its list; len[p] = its length. One thread per edge.
+__global__ void k_w24_len(uint64_t m, const uint64_t *__restrict__ wp,
+                          const uint32_t *__restrict__ wc, const uint32_t *__restrict__ wt,
+                          const uint32_t *__restrict__ te, uint32_t *__restrict__ len,
+                          uint32_t *__restrict__ sel) {
+  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < m;
+       e += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t b = wp[e], f = wp[e + 1];
+    for (uint64_t p = b; p < f; p++) {
+      const uint32_t w = wc[p];
+      const uint64_t t = wt[p];
+      uint32_t xs[2], nx = 0;
+      for (int q = 0; q < 3; q++) {
+        const uint32_t z = te[3 * t + q];
+        if (z != (uint32_t)e && nx < 2) xs[nx++] = z;
+      }
+      uint64_t best = f - p - 1;   // W(e) above w: the entries after p
+      uint32_t bsel = 0, boff = (uint32_t)(p + 1 - b);
+      for (int q = 0; q < 2; q++) {
+        const uint64_t lb = wp[xs[q]], lf = wp[xs[q] + 1];
+        const uint64_t first = upper_bound_u32(wc, lb, lf, w);
+        if (lf - first < best) {
+          best = lf - first;
+          bsel = (uint32_t)q + 1;
+          boff = (uint32_t)(first - lb);
+        }
+      }
+      len[p] = (uint32_t)best;
+      sel[p] = (bsel << 30) | boff;
     }
-    len3[p] = (uint32_t)mn;
   }
 }
 
@@ -564,7 +584,7 @@ nd_status nd_stage_prep(nd_ctx *c, GraphView *gv) {
     if (st != ND_OK) return st;
     st = nd_hip(c, hipMemsetAsync(&sc->barrier, 0, 8, c->stream), "memset barrier");
     if (st != ND_OK) return st;
-    OrientArgs oa;
+    OrientArgs oa{};
     oa.n = n;
     oa.rp = rp;
     oa.col = col;
@@ -612,6 +632,7 @@ nd_status nd_stage_prep(nd_ctx *c, GraphView *gv) {
 
   const bool tri_tables = c->r == 3 || (c->r == 2 && c->s == 4);
   gv->wg = nullptr;
+  gv->wsel = nullptr;
   if (tri_tables && m) {
     uint32_t *sup = (uint32_t *)nd_buf(c, B_SUP, m * 4, &st);
     if (!sup) return st;
@@ -651,19 +672,22 @@ nd_status nd_stage_prep(nd_ctx *c, GraphView *gv) {
       // (2,4): probe length of every W entry's triangle, summed over all
       // entries, so a peeled edge can hand out the candidate 4th vertices of
       // all its triangles as one flat range
-      uint32_t *len3 = (uint32_t *)nd_buf(c, B_W24L, std::max<uint64_t>(nw, 1) * 4, &st);
+      uint32_t *len3 = (uint32_t *)nd_buf(c, B_TMP32D, std::max<uint64_t>(nw, 1) * 4, &st);
       if (!len3) return st;
+      uint32_t *wsel = (uint32_t *)nd_buf(c, B_W24L, std::max<uint64_t>(nw, 1) * 4, &st);
+      if (!wsel) return st;
       uint64_t *wg = (uint64_t *)nd_buf(c, B_WG, (nw + 1) * 8, &st);
       if (!wg) return st;
       if (nw)
-        hipLaunchKernelGGL(k_w24_len, dim3(nd_grid(nw, 256, 65536)), dim3(256), 0, c->stream, nw,
-                           wt, te, wp, len3);
+        hipLaunchKernelGGL(k_w24_len, dim3(nd_grid(m, 256, 16384)), dim3(256), 0, c->stream, m,
+                           wp, wc, wt, te, len3, wsel);
       uint64_t total = 0;
       st = nd_exclusive_scan_u32_to_u64(c, len3, wg, nw, &total);
       if (st != ND_OK) return st;
       hipLaunchKernelGGL(k_w24_check, dim3(nd_grid(m, 256, 16384)), dim3(256), 0, c->stream, m,
                          wp, wg, &sc->status);
       gv->wg = wg;
+      gv->wsel = wsel;
     }
   } else if (c->r == 3) {
     c->n_r = 0;

@@ -39,6 +39,8 @@ ND_MEM_HOST = 0
 ND_MEM_DEVICE = 1
 
 ND_FLAG_PROGRESS = 1
+ND_FLAG_HIER_EL = 2
+ND_FLAG_HIER_TE = 4
 
 NONE64 = np.uint64(0xFFFFFFFFFFFFFFFF)
 
@@ -91,6 +93,9 @@ class Info(C.Structure):
         ("ms_count_kernel", C.c_float),
         ("ms_peel_kernel", C.c_float),
         ("device_bytes", C.c_uint64),
+        ("hier_te", C.c_uint32),
+        ("ms_hier", C.c_float),
+        ("hier_visits", C.c_uint64),
     ]
 
     def as_dict(self) -> dict:
@@ -267,7 +272,8 @@ class Context:
 
     def __init__(self, device: int = 0, stream=None, validate: bool = True, mem_limit: int = 0,
                  peel_blocks: int = 0, work_chunk: int = 0, watchdog: int = 0,
-                 use_torch_stream: bool = True, progress: bool = False):
+                 use_torch_stream: bool = True, progress: bool = False,
+                 hierarchy: str = "auto"):
         self.lib = load_library()
         opt = Options()
         opt.device = device
@@ -279,7 +285,8 @@ class Context:
         opt.peel_blocks = peel_blocks
         opt.work_chunk = work_chunk
         opt.watchdog = watchdog
-        opt.flags = ND_FLAG_PROGRESS if progress else 0
+        opt.flags = (ND_FLAG_PROGRESS if progress else 0) | \
+            {"auto": 0, "el": ND_FLAG_HIER_EL, "te": ND_FLAG_HIER_TE}[hierarchy]
         h = C.c_void_p()
         st = self.lib.nd_create(C.byref(h), C.byref(opt))
         if st != ND_OK:

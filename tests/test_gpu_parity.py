@@ -139,3 +139,19 @@ def test_progress_reports(capfd):
     for tag in ("prep queued", "count done", "peel done", "tree done"):
         assert f"[nd] {tag}" in err, err
     assert f"n_s={res.info['n_s']}" in err
+
+
+@pytest.mark.parametrize("mode", ["el", "te"])
+@pytest.mark.parametrize("r,s", RS)
+def test_hierarchy_modes(r, s, mode):
+    """Algorithm 5 during the peel (EL) and the descending-core build after
+    it (TE) give the oracle's canonical tree for every pair."""
+    from paper_2306_08623_amd import nucleus
+    graphs = [(I.workload_er2k(), "er2k"), (I.er_planted(600, 0.015, 8, 5, 18, 2), "planted600"),
+              (I.two_k5_bridge(), "two-K5"), (I.complete(7), "K7")]
+    if (r, s) != (2, 4):
+        graphs.append((I.rmat(12, 16, seed=7), "rmat12"))
+    with nucleus.Context(device=0, hierarchy=mode) as c2:
+        for g, name in graphs:
+            res, d = check(c2, g, r, s, f"{name}/{mode}")
+            assert res.info["hier_te"] == (1 if mode == "te" else 0)
