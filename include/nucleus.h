@@ -120,6 +120,8 @@ typedef struct nd_info {
   uint32_t hier_te;       /* 1 if the hierarchy was built by the TE pass      */
   float ms_hier;          /* TE: device time of level sort + hierarchy kernel */
   uint64_t hier_visits;   /* TE: s-cliques met by the hierarchy kernel        */
+  uint32_t grid_retries;  /* persistent launches repeated with a smaller grid
+                             because the first was not fully resident         */
 } nd_info;
 
 /* Create a context on opt->device (opt may be NULL: device 0, null stream,

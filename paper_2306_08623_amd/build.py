@@ -56,7 +56,7 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + f".tmp{os.getpid()}"
     rpath = ":".join(_runtime_dirs())
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs,
-           f"-Wl,-rpath,{rpath}", "-Wl,--disable-new-dtags", "-o", tmp]
+           f"-Wl,-rpath,{rpath}", "-Wl,--disable-new-dtags", "-Wl,-z,defs", "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)

@@ -67,15 +67,6 @@ void *nd_buf(nd_ctx *c, int id, size_t bytes, nd_status *st) {
   return p;
 }
 
-nd_status nd_coop_launch(nd_ctx *c, const void *kern, dim3 grid, dim3 block, void **args,
-                         hipEvent_t before, hipEvent_t after, const char *what) {
-  if (before) (void)hipEventRecord(before, c->stream);
-  nd_status st =
-      nd_hip(c, hipLaunchCooperativeKernel(kern, grid, block, args, 0, c->stream), what);
-  if (after) (void)hipEventRecord(after, c->stream);
-  return st;
-}
-
 void nd_report(nd_ctx *c, const char *fmt, ...) {
   if (!(c->flags & ND_FLAG_PROGRESS)) return;
   char buf[512];
@@ -104,6 +95,46 @@ void nd_report_while_running(nd_ctx *c, const char *phase, const uint32_t *progr
       nd_report(c, "%s running %.0f s: round %u, level %u, frontier %u", phase,
                 std::chrono::duration<double>(now - t0).count(), p[0], p[1], p[2]);
     }
+  }
+}
+
+nd_status nd_coop_launch(nd_ctx *c, const void *kern, uint32_t *nb, uint32_t *nb_arg,
+                         dim3 block, void **args, hipEvent_t before, hipEvent_t after,
+                         const char *what) {
+  DevScalars *sc = (DevScalars *)c->bufs[B_SCAL].p;
+  for (;;) {
+    *nb_arg = *nb;
+    nd_status st = nd_hip(c, hipMemsetAsync(&sc->barrier, 0, 8, c->stream), "barrier reset");
+    if (st != ND_OK) return st;
+    if (before) (void)hipEventRecord(before, c->stream);
+    st = nd_hip(c, hipLaunchCooperativeKernel(kern, dim3(*nb), block, args, 0, c->stream), what);
+    if (after) (void)hipEventRecord(after, c->stream);
+    if (st != ND_OK) return st;
+    if (c->report_phase && c->progress) nd_report_while_running(c, c->report_phase, c->progress);
+    uint32_t status = 0;
+    if ((st = nd_hip(c, hipMemcpyAsync(&status, &sc->status, 4, hipMemcpyDeviceToHost,
+                                       c->stream), what)) != ND_OK ||
+        (st = nd_hip(c, hipStreamSynchronize(c->stream), what)) != ND_OK)
+      return st;
+    if (!(status & ND_DERR_RESIDENCY)) {
+      if (c->info.grid_retries) {   // remember what fitted, for later launches
+        bool found = false;
+        for (auto &e : c->resident_cap)
+          if (e.first == kern) { e.second = std::min(e.second, *nb); found = true; }
+        if (!found) c->resident_cap.emplace_back(kern, *nb);
+      }
+      return ND_OK;
+    }
+    // not resident: nothing was written before the gate; clear and shrink
+    c->info.grid_retries++;
+    nd_report(c, "%s: grid of %u workgroups not resident, retrying smaller", what, *nb);
+    const uint32_t zero = 0;
+    if ((st = nd_hip(c, hipMemcpyAsync(&sc->status, &zero, 4, hipMemcpyHostToDevice, c->stream),
+                     "status reset")) != ND_OK ||
+        (st = nd_hip(c, hipStreamSynchronize(c->stream), "status reset")) != ND_OK)
+      return st;
+    if (*nb <= 1) return nd_fail(c, ND_E_DEVICE, std::string(what) + ": no resident grid");
+    *nb = std::max<uint32_t>(1, *nb / 4 * 3);
   }
 }
 

@@ -412,6 +412,7 @@ static void add_info(nd_info &T, const nd_info &I) {
   T.hier_te |= I.hier_te;
   T.ms_hier += I.ms_hier;
   T.hier_visits += I.hier_visits;
+  T.grid_retries += I.grid_retries;
 }
 
 // Host half of a batch: checks, grouping by (r,s) and, for host inputs, the

@@ -21,6 +21,7 @@
 #define ND_DERR_LINKQ 2u
 #define ND_DERR_BADGRAPH 4u
 #define ND_DERR_OVERFLOW 8u
+#define ND_DERR_RESIDENCY 16u   // a persistent grid was not fully resident
 
 // ---------------------------------------------------------------------------
 // Device views (plain pointers, passed by value to kernels)
@@ -191,6 +192,37 @@ __device__ __forceinline__ bool grid_barrier(uint64_t *bar, uint32_t nblocks, ui
   return s_ok != 0;
 }
 
+// First step of every persistent (grid-barrier) kernel, before it touches
+// any state: all workgroups must arrive within 200 ms, else the grid is not
+// fully resident (the device cannot run all of its workgroups at once) and
+// every workgroup leaves with ND_DERR_RESIDENCY, so that the host relaunches
+// a smaller grid instead of the barriers waiting out their watchdog.
+constexpr uint64_t kResidencyTicks = 20000000ull;
+
+__device__ __forceinline__ bool residency_gate(uint64_t *bar, uint32_t nblocks,
+                                               uint32_t *status) {
+  __syncthreads();
+  __shared__ uint32_t s_in;
+  if (threadIdx.x == 0) {
+    atomicAdd((unsigned long long *)bar, 1ull);
+    uint32_t ok = 1;
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    while (ld_acq64(bar) < (uint64_t)nblocks) {
+      if (ld_acq32(status) != 0) { ok = 0; break; }
+      if (__builtin_amdgcn_s_memrealtime() - t0 > kResidencyTicks) {
+        atomicOr(status, ND_DERR_RESIDENCY);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __threadfence();
+    s_in = ok;
+  }
+  __syncthreads();
+  return s_in != 0;
+}
+
 // ---------------------------------------------------------------------------
 // Host context
 // ---------------------------------------------------------------------------
@@ -212,6 +244,9 @@ struct nd_ctx {
   uint64_t watchdog = 0;
   uint32_t flags = 0;          // ND_FLAG_*
   uint32_t *progress = nullptr;   // pinned host words the peel kernel updates
+  const char *report_phase = nullptr;   // name of the running persistent launch
+  // largest grid of each persistent kernel found resident on this device
+  std::vector<std::pair<const void *, uint32_t>> resident_cap;
   int cu_count = 0;
   std::string last_error;
 
@@ -302,10 +337,14 @@ nd_status nd_fail(nd_ctx *c, nd_status st, const std::string &msg);
 void *nd_buf(nd_ctx *c, int id, size_t bytes, nd_status *st);
 nd_status nd_hip(nd_ctx *c, hipError_t e, const char *what);
 
-// cooperative (grid-barrier) launch on the context's stream; `before` /
-// `after` (may be null) are recorded around it
-nd_status nd_coop_launch(nd_ctx *c, const void *kern, dim3 grid, dim3 block, void **args,
-                         hipEvent_t before, hipEvent_t after, const char *what);
+// Cooperative (grid-barrier) launch of a kernel that opens with
+// residency_gate: *nb workgroups (the kernel reads the count from *nb_arg),
+// the barrier counter reset first; if the grid turns out not to be resident
+// it is relaunched with 3/4 of the workgroups (waits for the launch).
+// `before` / `after` (may be null) are recorded around the last attempt.
+nd_status nd_coop_launch(nd_ctx *c, const void *kern, uint32_t *nb, uint32_t *nb_arg,
+                         dim3 block, void **args, hipEvent_t before, hipEvent_t after,
+                         const char *what);
 
 // releases the host state of the last batch (nd_batch.hip)
 void nd_batch_release(nd_ctx *c);

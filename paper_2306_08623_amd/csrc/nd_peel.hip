@@ -473,7 +473,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
   lc.unites = 0;
   uint64_t visits = 0, decs = 0, scans = 0, calls = 0;
   for (uint32_t i = threadIdx.x; i < kLinkCache; i += kPeelBlock) s_lcache[i] = ~0ull;
-  __syncthreads();
+  if (!residency_gate(&sc->barrier, nb, &sc->status)) return;
 
   uint32_t k = 0;
   uint32_t t = 0;
@@ -831,6 +831,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_hier(HierArgs a) {
   const uint64_t gtid = blockIdx.x * (uint64_t)kPeelBlock + threadIdx.x;
   const uint64_t nthreads = (uint64_t)nb * kPeelBlock;
   uint64_t visits = 0, pairs = 0, unites = 0;
+  if (!residency_gate(&sc->barrier, nb, &sc->status)) return;
 
   for (uint32_t c = a.k; c >= 1; c--) {
     const uint64_t fb = a.loff[a.k - c], fe = a.loff[a.k - c + 1];
@@ -951,7 +952,11 @@ __global__ void k_iota(uint32_t *a, uint64_t n) {
     a[i] = (uint32_t)i;
 }
 
-// persistent grid: as many workgroups as fit on the device at once
+// persistent grid: as many workgroups as fit on the device at once. The
+// occupancy query is bounded by the kernel's registers at a 16-register
+// allocation granule (the query's own figure was not resident for a
+// 68-register kernel), and by the largest grid this context has seen
+// resident; the kernels' residency gate catches anything still too large.
 template <typename K>
 uint32_t coop_grid(nd_ctx *c, K kern, uint32_t *nb) {
   int per_cu = 0;
@@ -959,7 +964,18 @@ uint32_t coop_grid(nd_ctx *c, K kern, uint32_t *nb) {
           hipSuccess ||
       per_cu < 1)
     return 0;
+  hipFuncAttributes fa;
+  if (hipFuncGetAttributes(&fa, (const void *)kern) == hipSuccess && fa.numRegs > 0) {
+    const int regs = (fa.numRegs + 15) / 16 * 16;
+    const int waves_per_simd = std::min(8, 512 / regs);
+    const int waves_per_block = kPeelBlock / 64;
+    per_cu = std::max(1, std::min(per_cu, waves_per_simd * 4 / waves_per_block));
+  } else {
+    (void)hipGetLastError();
+  }
   uint64_t cap = (uint64_t)per_cu * (uint64_t)c->cu_count;
+  for (const auto &e : c->resident_cap)
+    if (e.first == (const void *)kern) cap = std::min<uint64_t>(cap, e.second);
   cap = std::min<uint64_t>(cap, kMaxPeelBlocks);
   uint64_t want = c->peel_blocks ? c->peel_blocks : cap;
   *nb = (uint32_t)std::max<uint64_t>(1, std::min(want, cap));
@@ -972,12 +988,12 @@ nd_status launch_peel(nd_ctx *c, PeelArgs &pa) {
   uint32_t nb = 0;
   if (!coop_grid(c, k_peel<R_, S_, kLink>, &nb))
     return nd_fail(c, ND_E_DEVICE, "occupancy query failed for the peel kernel");
-  pa.nblocks = nb;
   void *args[] = {&pa};
-  nd_status st = nd_coop_launch(c, kern, dim3(nb), dim3(kPeelBlock), args,
+  if (pa.progress) c->report_phase = "peel";
+  nd_status st = nd_coop_launch(c, kern, &nb, &pa.nblocks, dim3(kPeelBlock), args,
                                 c->events_ok ? c->ev[5] : nullptr,
                                 c->events_ok ? c->ev[6] : nullptr, "peel launch");
-  if (st == ND_OK && pa.progress) nd_report_while_running(c, "peel", pa.progress);
+  c->report_phase = nullptr;
   return st;
 }
 
@@ -1027,18 +1043,16 @@ nd_status run_te(nd_ctx *c, PeelArgs &pa) {
                      pa.cnt, k, loff, hist, pa.F0);
   hipLaunchKernelGGL(k_iota, dim3(nd_grid(nr, 256, 16384)), dim3(256), 0, c->stream, pa.al0, nr);
   hipLaunchKernelGGL(k_iota, dim3(nd_grid(nr, 256, 16384)), dim3(256), 0, c->stream, pa.al1, nr);
-  if ((st = nd_hip(c, hipMemsetAsync(&sc->barrier, 0, 8, c->stream), "barrier")) != ND_OK)
-    return st;
   if ((st = nd_hip(c, hipGetLastError(), "level sort")) != ND_OK) return st;
   if (pa.progress) memset(pa.progress, 0, 4 * sizeof(uint32_t));
   uint32_t nb = 0;
   if (!coop_grid(c, k_hier<R_, S_>, &nb))
     return nd_fail(c, ND_E_DEVICE, "occupancy query failed for the hierarchy kernel");
-  h.nblocks = nb;
   void *args[] = {&h};
-  st = nd_coop_launch(c, (const void *)k_hier<R_, S_>, dim3(nb), dim3(kPeelBlock), args,
+  if (h.progress) c->report_phase = "hierarchy";
+  st = nd_coop_launch(c, (const void *)k_hier<R_, S_>, &nb, &h.nblocks, dim3(kPeelBlock), args,
                       nullptr, c->events_ok ? c->ev[9] : nullptr, "hierarchy launch");
-  if (st == ND_OK && h.progress) nd_report_while_running(c, "hierarchy", h.progress);
+  c->report_phase = nullptr;
   return st;
 }
 

@@ -205,6 +205,7 @@ __global__ void __launch_bounds__(kOrientBlock) k_orient(OrientArgs a) {
   __shared__ uint64_t s_left[kOrientBlock / 64], s_sum[kOrientBlock / 64];
   const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t nth = gridDim.x * blockDim.x;
+  if (!residency_gate(&a.sc->barrier, a.nblocks, &a.sc->status)) return;
   for (uint32_t round = 0;; round++) {
     uint64_t *cur = a.sums + 2 * (round & 1);
     uint64_t *nxt = a.sums + 2 * ((round + 1) & 1);
@@ -594,10 +595,9 @@ nd_status nd_stage_prep(nd_ctx *c, GraphView *gv) {
     oa.sums = sums;
     uint32_t nb = coop_blocks(c, (const void *)k_orient, kOrientBlock,
                               (uint32_t)std::min<uint64_t>(2048, (n + kOrientBlock - 1) / kOrientBlock));
-    oa.nblocks = nb;
     void *args[] = {&oa};
-    st = nd_coop_launch(c, (const void *)k_orient, dim3(nb), dim3(kOrientBlock), args, nullptr,
-                        nullptr, "orientation launch");
+    st = nd_coop_launch(c, (const void *)k_orient, &nb, &oa.nblocks, dim3(kOrientBlock), args,
+                        nullptr, nullptr, "orientation launch");
     if (st != ND_OK) return st;
   }
   uint32_t *dgcnt = upcnt;   // reuse

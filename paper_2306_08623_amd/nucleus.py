@@ -96,6 +96,7 @@ class Info(C.Structure):
         ("hier_te", C.c_uint32),
         ("ms_hier", C.c_float),
         ("hier_visits", C.c_uint64),
+        ("grid_retries", C.c_uint32),
     ]
 
     def as_dict(self) -> dict:
