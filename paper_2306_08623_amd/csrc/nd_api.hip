@@ -87,7 +87,7 @@ void nd_report_while_running(nd_ctx *c, const char *phase, const uint32_t *progr
       if (q != hipSuccess) (void)hipGetLastError();   // reported by the next sync
       return;
     }
-    std::this_thread::sleep_for(std::chrono::milliseconds(50));
+    std::this_thread::sleep_for(std::chrono::milliseconds(1));
     const auto now = std::chrono::steady_clock::now();
     if (now - last >= std::chrono::seconds(10)) {
       last = now;
