@@ -118,6 +118,107 @@ __device__ __forceinline__ void spill(LinkCtx &c, uint32_t R, uint32_t Q) {
 
 __device__ __forceinline__ uint64_t min64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 
+// One step of LINK-EFFICIENT (Algorithm 5) on the pair (R, Q): the same
+// transitions as link_efficient below, but the recursive calls it makes
+// (at most two) are returned in out[] instead of being run, so that a whole
+// wave can work through a queue of pending steps together.
+__device__ __forceinline__ uint32_t link_step(LinkCtx &c, uint32_t R, uint32_t Q, uint64_t *out) {
+  uint32_t no = 0;
+  auto push = [&](uint32_t a, uint32_t b) {
+    if (a != ND_NONE && b != ND_NONE) out[no++] = ((uint64_t)a << 32) | b;
+  };
+  if (R == ND_NONE || Q == ND_NONE) return 0;
+  c.links++;
+  if (c.nd[Q] < c.nd[R]) { uint32_t t = R; R = Q; Q = t; }
+  R = uf_find(c.uf, R);
+  Q = uf_find(c.uf, Q);
+  const uint32_t ndR = c.nd[R];
+  if (ndR == c.nd[Q]) {
+    if (R == Q) return 0;
+    const uint32_t loser = uf_unite(c.uf, R, Q);   // hand-over as in link_efficient
+    if (loser != ND_NONE) {
+      c.unites++;
+      const uint32_t w = uf_find(c.uf, loser);
+      push(ld_acq32(&c.L[loser]), w);
+    }
+    return no;
+  }
+  for (uint32_t spins = 0;; spins++) {
+    if (spins > kLinkStepCap) {
+      atomicOr(&c.sc->status, ND_DERR_WATCHDOG);
+      return no;
+    }
+    Q = uf_find(c.uf, Q);
+    const uint32_t LQ = ld_acq32(&c.L[Q]);
+    if (LQ == ND_NONE) {
+      if (cas32(&c.L[Q], ND_NONE, R)) {
+        const uint32_t pQ = uf_find(c.uf, Q);
+        if (pQ != Q) push(R, pQ);
+        return no;
+      }
+      continue;
+    }
+    if (c.nd[LQ] < ndR) {
+      if (cas32(&c.L[Q], LQ, R)) {
+        const uint32_t pQ = uf_find(c.uf, Q);
+        if (pQ != Q) push(R, pQ);
+        push(R, LQ);
+        return no;
+      }
+    } else {
+      push(R, LQ);
+      return no;
+    }
+  }
+}
+
+// Per-wave LDS queue of pending link steps (pairs R << 32 | Q); `qn` is the
+// same in every lane. Each pass gives one pending step to each lane.
+constexpr uint32_t kWaveQ = 128;
+
+// appends one optional pair per lane; the caller leaves room for 64
+__device__ __forceinline__ void wave_q_push(uint64_t *q, uint32_t &qn, bool has, uint64_t v) {
+  const uint64_t m = ballot64(has);
+  if (has) {
+    const uint32_t lane = lane_id();
+    const uint64_t below = m & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)));
+    q[qn + __popcll(below)] = v;
+  }
+  qn += __popcll(m);
+  __builtin_amdgcn_wave_barrier();
+}
+
+// runs queued steps while at least `need` are pending (need = 1: until empty)
+__device__ void wave_q_drain(LinkCtx &c, uint64_t *q, uint32_t &qn, uint32_t need) {
+  const uint32_t lane = lane_id();
+  uint32_t passes = 0;
+  while (qn >= need && qn > 0) {
+    if (++passes > kLinkStepCap) {   // a runaway cascade: give up with an error
+      if (lane == 0) atomicOr(&c.sc->status, ND_DERR_WATCHDOG);
+      qn = 0;
+      break;
+    }
+    const uint32_t take = qn < 64 ? qn : 64;
+    uint64_t mine = ~0ull;
+    if (lane < take) mine = q[qn - take + lane];
+    __builtin_amdgcn_wave_barrier();
+    qn -= take;
+    uint64_t out[2];
+    uint32_t no = 0;
+    if (mine != ~0ull) no = link_step(c, (uint32_t)(mine >> 32), (uint32_t)mine, out);
+#pragma unroll
+    for (int o = 0; o < 2; o++) {
+      const bool has = (uint32_t)o < no;
+      const uint32_t cnt = __popcll(ballot64(has));
+      if (qn + cnt <= kWaveQ) {
+        wave_q_push(q, qn, has, has ? out[o] : 0);
+      } else if (has) {
+        spill(c, (uint32_t)(out[o] >> 32), (uint32_t)out[o]);
+      }
+    }
+  }
+}
+
 // LINK-EFFICIENT (Algorithm 5) for the pair (R0, Q0), whose core numbers are
 // both final. Recursive calls are pushed on a small stack; pairs that do not
 // fit go to the global queue.
@@ -453,6 +554,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
   __shared__ uint32_t s_cnt[kPeelBlock / 64];
   __shared__ uint64_t s_red64[kPeelBlock / 64];
   __shared__ uint64_t s_lcache[kLinkCache];
+  __shared__ uint64_t s_lq[kLink ? kPeelBlock / 64 : 1][kLink ? kWaveQ : 1];
 
   DevScalars *sc = a.sc;
   const GraphView &g = a.g;
@@ -632,13 +734,19 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
       __syncthreads();
     }
     const uint64_t P = s_boff[nb];
+    uint64_t *wq = s_lq[kLink ? wv : 0];
+    uint32_t qn = 0;   // pending link steps of this wave (uniform)
     for (uint64_t base = blockIdx.x * (uint64_t)kPeelBlock + wv * 64ull; base < P;
          base += nthreads) {
       const uint64_t p = base + lane;
       uint32_t others[NO];
       bool push[NO];
+      uint64_t lpair[NO];   // link calls of this lane's probe, queued below
 #pragma unroll
-      for (int j = 0; j < NO; j++) push[j] = false;
+      for (int j = 0; j < NO; j++) {
+        push[j] = false;
+        lpair[j] = ~0ull;
+      }
       if (p < P) {
         // block segment holding unit p, then the frontier slot inside it
         uint32_t lo = 0, hi = nb;   // s_boff[lo] <= p < s_boff[hi]
@@ -703,7 +811,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
                 continue;
               }
               calls++;
-              link_efficient(lc, others[j], R);
+              lpair[j] = ((uint64_t)others[j] << 32) | R;
               lcache_put(s_lcache, x, qroot);
               atomicExch((unsigned long long *)gslot, (unsigned long long)key);
             }
@@ -715,7 +823,18 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
         uint32_t slot = wave_append(&sc->fsize[(t + 1) & 1], push[j]);
         if (push[j]) Fn[slot] = others[j];
       }
+      if (kLink) {
+        // queue this pass's link calls; run them whenever a full pass of
+        // 64 steps is pending
+#pragma unroll
+        for (int j = 0; j < NO; j++) {
+          if (qn > kWaveQ - 64) wave_q_drain(lc, wq, qn, 64);
+          wave_q_push(wq, qn, lpair[j] != ~0ull, lpair[j]);
+        }
+        wave_q_drain(lc, wq, qn, 64);
+      }
     }
+    if (kLink) wave_q_drain(lc, wq, qn, 1);
     if (!grid_barrier(&sc->barrier, nb, &sc->status)) break;
 
     // ---- drain spilled link pairs (rare): repeat until the queue is empty
