@@ -58,8 +58,10 @@ def _check(g, r, s, res, n_sample):
     assert np.all(core <= counts)
     _say(f"[cl4m] ({r},{s}): oracle listing of the r-cliques")
     G = oracle.Graph(g, r, s)
+    _say(f"[cl4m] ({r},{s}): oracle listed {G.n_r} r-cliques")
     assert G.n_r == n_r
     assert np.array_equal(G.rcliques(), res["rcl"])
+    _say(f"[cl4m] ({r},{s}): listings equal")
     rng = np.random.default_rng(10 * r + s)
     small = np.nonzero(counts <= 200_000)[0]
     sample = rng.choice(small, size=min(small.size, n_sample), replace=False)
