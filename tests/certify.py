@@ -90,19 +90,40 @@ def check_tree_properties(parent, level, core, n_r):
 
 
 def ancestor_at(parent, level, n_r, x, c):
-    """Deepest ancestor node of leaves x with level <= c (-1 if none)."""
+    """Deepest ancestor node of leaves x with level <= c (-1 if none).
+
+    Levels strictly decrease towards the root, so the answer is found by
+    binary lifting: jump tables of 2^j-th ancestors over the internal nodes
+    (hierarchies can be tens of thousands of levels deep)."""
     par = parent.astype(np.int64)
     par[parent == NONE] = -1
     lev = level.astype(np.int64)
-    node = par[np.asarray(x, dtype=np.int64)]
+    n_int = lev.size
+    node = par[np.asarray(x, dtype=np.int64)]          # first internal node (or -1)
     c = np.asarray(c, dtype=np.int64)
-    while True:
-        ok = node >= 0
-        need = np.zeros(node.shape, dtype=bool)
-        need[ok] = lev[node[ok] - n_r] > c[ok]
-        if not need.any():
-            return node
-        node[need] = par[node[need]]
+    if n_int == 0:
+        return node
+    up = [np.where(par[n_r:] >= 0, par[n_r:] - n_r, -1)]   # parent among nodes, -1 at roots
+    while len(up) < 64:
+        prev = up[-1]
+        nxt = np.where(prev >= 0, prev[np.maximum(prev, 0)], -1)
+        if np.array_equal(nxt, prev):
+            break
+        up.append(nxt)
+    cur = np.where(node >= 0, node - n_r, -1)
+    # climb while the node's level is above c: highest jumps first, only to
+    # ancestors still above c; then one more step to the parent
+    above = np.zeros(cur.shape, dtype=bool)
+    ok = cur >= 0
+    above[ok] = lev[cur[ok]] > c[ok]
+    for tab in reversed(up):
+        cand = np.where(above, tab[np.maximum(cur, 0)], -1)
+        take = above & (cand >= 0)
+        take[take] = lev[cand[take]] > c[take]
+        cur = np.where(take, cand, cur)
+    step = np.where(above, up[0][np.maximum(cur, 0)], cur)
+    res = np.where(step >= 0, step + n_r, -1)
+    return res
 
 
 def check_adjacency_closure(G, parent, level, core, n_r, sample):

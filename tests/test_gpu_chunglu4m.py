@@ -72,8 +72,10 @@ def _check(g, r, s, res, n_sample):
     certify.check_core_certificates(G, core, res["rounds"], counts, sample)
     _say(f"[cl4m] ({r},{s}): tree properties")
     certify.check_tree_properties(res["parent"], res["level"], core, n_r)
-    npairs = certify.check_adjacency_closure(G, res["parent"], res["level"], core, n_r,
-                                             sample[:400])
+    closure = sample[counts[sample] <= 5000][:400]
+    _say(f"[cl4m] ({r},{s}): adjacency closure from {closure.size} r-cliques")
+    npairs = certify.check_adjacency_closure(G, res["parent"], res["level"], core, n_r, closure)
+    _say(f"[cl4m] ({r},{s}): small nodes")
     nodes = certify.check_small_nodes_connected(G, res["parent"], res["level"], core, n_r,
                                                 max_nodes=10)
     _say(f"[cl4m] ({r},{s}): {npairs} adjacent pairs closed, {nodes} small nodes connected")
