@@ -27,7 +27,8 @@ pytestmark = pytest.mark.gpu
 
 
 def _say(msg):
-    print(msg, flush=True)
+    from conftest import progress
+    progress(msg)
 
 
 @pytest.fixture(scope="module")

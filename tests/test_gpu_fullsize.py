@@ -33,7 +33,8 @@ sys.path.insert(0, os.path.join(HERE, "golden"))
 
 
 def _say(msg):
-    print(msg, flush=True)
+    from conftest import progress
+    progress(msg)
 
 
 @pytest.fixture(scope="module")

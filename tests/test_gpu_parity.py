@@ -17,7 +17,8 @@ RS = [(1, 2), (2, 3), (3, 4), (2, 4)]
 
 
 def _say(msg):
-    print(msg, flush=True)
+    from conftest import progress
+    progress(msg)
     sys.stdout.flush()
 
 

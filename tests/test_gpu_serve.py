@@ -17,7 +17,8 @@ FIELDS = ("rcliques", "counts", "coreness", "parent", "level")
 
 
 def _say(msg):
-    print(msg, flush=True)
+    from conftest import progress
+    progress(msg)
 
 
 def _requests(count=48, m_hi=40_000):
