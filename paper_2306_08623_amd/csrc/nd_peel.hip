@@ -371,6 +371,34 @@ struct Shape<2, 3> {
   }
 };
 
+// (1,3): R = vertex v. A triangle {v, w, x} at v is taken from the CSR slot
+// v -> w of its smaller other vertex w, as the entry x > w of W(vw); the
+// probe entries of v are these, slot after slot (sg holds the running sums),
+// so every probe is a triangle. The other r-cliques are the vertices w, x.
+template <>
+struct Shape<1, 3> {
+  static constexpr int kOthers = 2;
+  __device__ static uint32_t len(const GraphView &g, uint32_t R) {
+    return (uint32_t)(g.sg[g.rp[R + 1]] - g.sg[g.rp[R]]);
+  }
+  __device__ static bool visit(const GraphView &g, uint32_t R, uint32_t i, uint32_t *o) {
+    const uint64_t b = g.rp[R], f = g.rp[R + 1];
+    const uint64_t target = g.sg[b] + i;
+    uint64_t lo = b, hi = f;   // last slot q with sg[q] <= target
+    while (hi - lo > 1) {
+      const uint64_t mid = (lo + hi) >> 1;
+      if (g.sg[mid] <= target) lo = mid;
+      else hi = mid;
+    }
+    const uint32_t w = g.col[lo], e = g.eid[lo];
+    const uint64_t wb = g.wp[e], wf = g.wp[e + 1];
+    const uint64_t first = upper_bound_u32(g.wc, wb, wf, w);
+    o[0] = w;
+    o[1] = g.wc[first + (target - g.sg[lo])];
+    return true;
+  }
+};
+
 // (3,4): R = triangle with edges e0, e1, e2; the common neighbours of its
 // vertices are the entries common to W(e0), W(e1), W(e2); the positions give
 // the ids of the three other triangles.
@@ -1240,5 +1268,6 @@ nd_status nd_stage_peel(nd_ctx *c, const GraphView &g) {
   if (r == 2 && s == 3) return te ? run_te<2, 3>(c, pa) : launch_peel<2, 3, true>(c, pa);
   if (r == 3 && s == 4) return te ? run_te<3, 4>(c, pa) : launch_peel<3, 4, true>(c, pa);
   if (r == 2 && s == 4) return te ? run_te<2, 4>(c, pa) : launch_peel<2, 4, true>(c, pa);
+  if (r == 1 && s == 3) return te ? run_te<1, 3>(c, pa) : launch_peel<1, 3, true>(c, pa);
   return nd_fail(c, ND_E_UNSUPPORTED, "peeling for this (r,s) is not built");
 }

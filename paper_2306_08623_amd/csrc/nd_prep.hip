@@ -508,6 +508,18 @@ __global__ void k_w24_len(uint64_t m, const uint64_t *__restrict__ wp,
   }
 }
 
+// (1,3): for CSR slot q = (v -> w), the entries of W(vw) above w
+__global__ void k_slot_tris(uint64_t nnz, const uint32_t *__restrict__ col,
+                            const uint32_t *__restrict__ eid, const uint64_t *__restrict__ wp,
+                            const uint32_t *__restrict__ wc, uint32_t *__restrict__ scnt) {
+  for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < nnz;
+       q += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t e = eid[q], w = col[q];
+    const uint64_t b = wp[e], f = wp[e + 1];
+    scnt[q] = (uint32_t)(f - upper_bound_u32(wc, b, f, w));
+  }
+}
+
 // an edge's probe range must stay below 2^32 entries (32-bit work items)
 __global__ void k_w24_check(uint64_t m, const uint64_t *__restrict__ wp,
                             const uint64_t *__restrict__ wg, uint32_t *status) {
@@ -630,9 +642,10 @@ nd_status nd_stage_prep(nd_ctx *c, GraphView *gv) {
   gv->wt = nullptr;
   gv->te = nullptr;
 
-  const bool tri_tables = c->r == 3 || (c->r == 2 && c->s == 4);
+  const bool tri_tables = c->r == 3 || (c->r == 2 && c->s == 4) || (c->r == 1 && c->s == 3);
   gv->wg = nullptr;
   gv->wsel = nullptr;
+  gv->sg = nullptr;
   if (tri_tables && m) {
     uint32_t *sup = (uint32_t *)nd_buf(c, B_SUP, m * 4, &st);
     if (!sup) return st;
@@ -668,6 +681,20 @@ nd_status nd_stage_prep(nd_ctx *c, GraphView *gv) {
     gv->wc = wc;
     gv->wt = wt;
     gv->te = te;
+    if (c->r == 1) {
+      // (1,3): per CSR slot v -> w, the triangles at v with smaller other
+      // vertex w (entries of W(vw) above w), summed over all slots
+      uint32_t *scnt = (uint32_t *)nd_buf(c, B_TMP32D, std::max<uint64_t>(nnz, 1) * 4, &st);
+      if (!scnt) return st;
+      uint64_t *sgl = (uint64_t *)nd_buf(c, B_SG, (nnz + 1) * 8, &st);
+      if (!sgl) return st;
+      hipLaunchKernelGGL(k_slot_tris, dim3(nd_grid(nnz, 256, 65536)), dim3(256), 0, c->stream, nnz,
+                         col, eid, wp, wc, scnt);
+      uint64_t total = 0;
+      st = nd_exclusive_scan_u32_to_u64(c, scnt, sgl, nnz, &total);
+      if (st != ND_OK) return st;
+      gv->sg = sgl;
+    }
     if (c->r == 2) {
       // (2,4): probe length of every W entry's triangle, summed over all
       // entries, so a peeled edge can hand out the candidate 4th vertices of

@@ -50,6 +50,8 @@ def _degenerate():
         (I.complete(7), 2, 4),
         (I.batch_graph(0)[0], 2, 4),
         (I.batch_graph(3)[0], 2, 4),
+        (I.batch_graph(5)[0], 1, 3),
+        (I.two_k5_bridge(), 1, 3),
     ]
 
 
@@ -132,7 +134,7 @@ def test_batch_errors(ctx):
         ctx.decompose_batch([(ok, 2, 3), (bad, 2, 3)])
     assert e.value.code == nucleus.ND_E_BAD_GRAPH
     with pytest.raises(nucleus.NucleusError) as e:
-        ctx.decompose_batch([(ok, 1, 3)])
+        ctx.decompose_batch([(ok, 1, 4)])
     assert e.value.code == nucleus.ND_E_UNSUPPORTED
     with pytest.raises(nucleus.NucleusError) as e:
         ctx.decompose_batch([(ok, 3, 3)])
