@@ -722,6 +722,13 @@ nd_status nd_stage_prep(nd_ctx *c, GraphView *gv) {
     c->n_r = m;
   } else {
     c->n_r = n;
+    if (c->s == 3) {
+      // no edges: every vertex's triangle range is empty (sg = {0})
+      uint64_t *sgl = (uint64_t *)nd_buf(c, B_SG, 8, &st);
+      if (!sgl) return st;
+      if ((st = nd_hip(c, hipMemsetAsync(sgl, 0, 8, c->stream), "sg")) != ND_OK) return st;
+      gv->sg = sgl;
+    }
   }
   return nd_hip(c, hipGetLastError(), "prep kernels");
 }
