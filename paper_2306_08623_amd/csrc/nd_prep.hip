@@ -664,7 +664,7 @@ nd_status nd_stage_prep(nd_ctx *c, GraphView *gv) {
     if (st != ND_OK) return st;
     if (ntri >= 0xFFFFFFFFull)
       return nd_fail(c, ND_E_OVERFLOW, "more than 2^32-2 triangles: 32-bit triangle ids overflow");
-    c->n_r = c->r == 3 ? ntri : m;
+    c->n_r = c->r == 3 ? ntri : (c->r == 2 ? m : n);
     uint32_t *wc = (uint32_t *)nd_buf(c, B_WC, std::max<uint64_t>(nw, 1) * 4, &st);
     if (!wc) return st;
     uint32_t *wt = (uint32_t *)nd_buf(c, B_WT, std::max<uint64_t>(nw, 1) * 4, &st);
