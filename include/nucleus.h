@@ -138,9 +138,9 @@ void nd_destroy(nd_ctx *ctx);
 nd_status nd_load_csr(nd_ctx *ctx, uint32_t n, uint64_t nnz, const uint64_t *row_ptr,
                       const uint32_t *col, nd_mem where);
 
-/* Choose (r,s): supported pairs are (1,2) (k-core), (2,3) (k-truss), (1,3),
- * (3,4) and (2,4). Other 1 <= r < s pairs return ND_E_UNSUPPORTED; r < 1 or
- * r >= s returns ND_E_INVALID_ARG. */
+/* Choose (r,s): supported pairs are every 1 <= r < s <= 4: (1,2) (k-core),
+ * (2,3) (k-truss), (1,3), (1,4), (2,4), (3,4). Pairs with s > 4 return
+ * ND_E_UNSUPPORTED; r < 1 or r >= s returns ND_E_INVALID_ARG. */
 nd_status nd_set_rs(nd_ctx *ctx, uint32_t r, uint32_t s);
 
 /* Run the whole pipeline on the context's stream: orientation, r-clique

@@ -438,7 +438,7 @@ nd_status nd_batch_plan(uint32_t G, const nd_graph_desc *graphs, nd_mem where,
     *err = "graph " + std::to_string(i) + ": " + what;
     return code;
   };
-  bool present[kBatchGroups] = {false, false, false, false, false};
+  bool present[kBatchGroups] = {false, false, false, false, false, false};
   for (uint32_t i = 0; i < G; i++) {
     const nd_graph_desc &d = graphs[i];
     if (d.r < 1 || d.s <= d.r) return fail_graph(i, ND_E_INVALID_ARG, "need 1 <= r < s");
@@ -461,7 +461,8 @@ nd_status nd_batch_plan(uint32_t G, const nd_graph_desc *graphs, nd_mem where,
     gidx[p] = (uint32_t)bs->groups.size();
     if (present[p]) {
       bs->groups.emplace_back();
-      static const uint32_t kR[kBatchGroups] = {1, 2, 3, 2, 1}, kS[kBatchGroups] = {2, 3, 4, 4, 3};
+      static const uint32_t kR[kBatchGroups] = {1, 2, 3, 2, 1, 1};
+      static const uint32_t kS[kBatchGroups] = {2, 3, 4, 4, 3, 4};
       bs->groups.back().r = kR[p];
       bs->groups.back().s = kS[p];
       bs->groups.back().slot = (int)p;

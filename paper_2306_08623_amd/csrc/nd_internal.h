@@ -52,9 +52,14 @@ struct GraphView {
   // running sum of the parts' lengths over all entries ([3 n_tri + 1])
   const uint32_t *wsel;
   const uint64_t *wg;
-  // (1,3) only: running sum over CSR slots v -> w of the entries of W(vw)
+  // (1,3), (1,4): running sum over CSR slots v -> w of the entries of W(vw)
   // above w (the triangles at v whose smaller other vertex is w); [2m + 1]
   const uint64_t *sg;
+  // (1,4) only, per triangle probe of (1,3) (global index sg[slot] + j):
+  // the probed list part for the 4th vertex y > x, as in wsel (list 0 =
+  // W(vw), 1 = W(vx), 2 = W(wx)), and the running sum of the parts' lengths
+  const uint32_t *tsel;
+  const uint64_t *tg;
 };
 
 // ---------------------------------------------------------------------------
@@ -292,7 +297,7 @@ enum BufId : int {
   B_SCAL, B_TMP64, B_TMP32A, B_TMP32B, B_TMP32C, B_TMP32D,
   B_SORTK0, B_SORTK1, B_SORTV0, B_SORTV1, B_HIST,
   B_PARENT, B_LEVEL, B_RCL, B_GCACHE, B_ACNT, B_NODEML, B_SORTOFF,
-  B_BATCHDESC, B_WG, B_W24L, B_LHIST, B_LOFF, B_SG,
+  B_BATCHDESC, B_WG, B_W24L, B_LHIST, B_LOFF, B_SG, B_TSEL, B_TG,
   B_COUNT
 };
 
@@ -304,17 +309,18 @@ inline bool nd_use_te(const nd_ctx *c);
 // the (r,s) pairs whose peel is built; index of a pair's batch slots
 inline bool nd_rs_supported(uint32_t r, uint32_t s) {
   return (r == 1 && s == 2) || (r == 2 && s == 3) || (r == 3 && s == 4) || (r == 2 && s == 4) ||
-         (r == 1 && s == 3);
+         (r == 1 && s == 3) || (r == 1 && s == 4);
 }
 inline int nd_rs_index(uint32_t r, uint32_t s) {
   if (r == 2 && s == 4) return 3;
   if (r == 1 && s == 3) return 4;
+  if (r == 1 && s == 4) return 5;
   return (int)r - 1;
 }
 
 // batch arena: per (r,s) group, kBatchFields grow-only slots after B_COUNT
 constexpr int kBatchFields = 10;
-constexpr int kBatchGroups = 5;   // (1,2), (2,3), (3,4), (2,4), (1,3)
+constexpr int kBatchGroups = 6;   // (1,2), (2,3), (3,4), (2,4), (1,3), (1,4)
 inline int nd_batch_slot(int group, int field) { return B_COUNT + group * kBatchFields + field; }
 
 // device scalars block (one per context)

@@ -399,6 +399,63 @@ struct Shape<1, 3> {
   }
 };
 
+// (1,4): R = vertex v. A 4-clique {v, w, x, y} with w < x < y is taken
+// from the triangle probe (v, w, x) of (1,3) with a 4th vertex y > x from
+// the shortest of the parts above x of W(vw), W(vx), W(wx) (chosen in prep:
+// tsel); tg holds the running sums over all triangle probes, so a vertex's
+// probe entries are one flat range. The other r-cliques are w, x, y.
+template <>
+struct Shape<1, 4> {
+  static constexpr int kOthers = 3;
+  __device__ static uint32_t len(const GraphView &g, uint32_t R) {
+    return (uint32_t)(g.tg[g.sg[g.rp[R + 1]]] - g.tg[g.sg[g.rp[R]]]);
+  }
+  __device__ static bool visit(const GraphView &g, uint32_t R, uint32_t i, uint32_t *o) {
+    const uint64_t gb = g.sg[g.rp[R]], gf = g.sg[g.rp[R + 1]];
+    const uint64_t target = g.tg[gb] + i;
+    uint64_t lo = gb, hi = gf;   // the triangle probe: last gi with tg[gi] <= target
+    while (hi - lo > 1) {
+      const uint64_t mid = (lo + hi) >> 1;
+      if (g.tg[mid] <= target) lo = mid;
+      else hi = mid;
+    }
+    const uint64_t gi = lo, jj = target - g.tg[gi];
+    uint64_t qlo = g.rp[R], qhi = g.rp[R + 1];   // its slot: last q with sg[q] <= gi
+    while (qhi - qlo > 1) {
+      const uint64_t mid = (qlo + qhi) >> 1;
+      if (g.sg[mid] <= gi) qlo = mid;
+      else qhi = mid;
+    }
+    const uint32_t w = g.col[qlo], e = g.eid[qlo];
+    const uint64_t b = g.wp[e], f = g.wp[e + 1];
+    const uint64_t p = upper_bound_u32(g.wc, b, f, w) + (gi - g.sg[qlo]);
+    const uint32_t x = g.wc[p], t = g.wt[p];
+    uint32_t evx = ND_NONE, ewx = ND_NONE;   // the triangle's edges {v,x}, {w,x}
+    for (int k = 0; k < 3; k++) {
+      const uint32_t z = g.te[3ull * t + k];
+      if (z == e) continue;
+      if (g.eu[z] == R || g.ev[z] == R) evx = z;
+      else ewx = z;
+    }
+    if (evx == ND_NONE || ewx == ND_NONE) return false;   // unreachable for consistent tables
+    const uint32_t sl = g.tsel[gi];
+    const uint32_t which = sl >> 30, off = sl & 0x3FFFFFFFu;
+    const uint32_t el[3] = {e, evx, ewx};
+    const uint32_t ep = el[which];
+    const uint32_t y = g.wc[g.wp[ep] + off + jj];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+      if ((uint32_t)k == which) continue;
+      const uint64_t lb = g.wp[el[k]], lf = g.wp[el[k] + 1];
+      if (find_u32<uint64_t>(g.wc, lb, lf, y) == lf) return false;
+    }
+    o[0] = w;
+    o[1] = x;
+    o[2] = y;
+    return true;
+  }
+};
+
 // (3,4): R = triangle with edges e0, e1, e2; the common neighbours of its
 // vertices are the entries common to W(e0), W(e1), W(e2); the positions give
 // the ids of the three other triangles.
@@ -1269,5 +1326,6 @@ nd_status nd_stage_peel(nd_ctx *c, const GraphView &g) {
   if (r == 3 && s == 4) return te ? run_te<3, 4>(c, pa) : launch_peel<3, 4, true>(c, pa);
   if (r == 2 && s == 4) return te ? run_te<2, 4>(c, pa) : launch_peel<2, 4, true>(c, pa);
   if (r == 1 && s == 3) return te ? run_te<1, 3>(c, pa) : launch_peel<1, 3, true>(c, pa);
+  if (r == 1 && s == 4) return te ? run_te<1, 4>(c, pa) : launch_peel<1, 4, true>(c, pa);
   return nd_fail(c, ND_E_UNSUPPORTED, "peeling for this (r,s) is not built");
 }

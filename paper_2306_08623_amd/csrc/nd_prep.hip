@@ -520,6 +520,66 @@ __global__ void k_slot_tris(uint64_t nnz, const uint32_t *__restrict__ col,
   }
 }
 
+// (1,4): one thread per CSR slot v -> w; for each triangle probe (entry x
+// above w of W(vw)) the shortest of the parts above x of W(vw), W(vx), W(wx)
+__global__ void k_t14_len(uint64_t nnz, const uint64_t *__restrict__ rp,
+                          const uint32_t *__restrict__ col, const uint32_t *__restrict__ eid,
+                          const uint32_t *__restrict__ eu, const uint32_t *__restrict__ ev,
+                          const uint64_t *__restrict__ wp,
+                          const uint32_t *__restrict__ wc, const uint32_t *__restrict__ wt,
+                          const uint32_t *__restrict__ te, const uint64_t *__restrict__ sg,
+                          uint32_t *__restrict__ tlen, uint32_t *__restrict__ tsel, uint32_t n) {
+  for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < nnz;
+       q += (uint64_t)gridDim.x * blockDim.x) {
+    // the row v of slot q
+    uint64_t lo = 0, hi = n;   // last v with rp[v] <= q
+    while (hi - lo > 1) {
+      const uint64_t mid = (lo + hi) >> 1;
+      if (rp[mid] <= q) lo = mid;
+      else hi = mid;
+    }
+    const uint32_t v = (uint32_t)lo, w = col[q], e = eid[q];
+    const uint64_t b = wp[e], f = wp[e + 1];
+    const uint64_t first = upper_bound_u32(wc, b, f, w);
+    uint64_t gi = sg[q];
+    for (uint64_t p = first; p < f; p++, gi++) {
+      const uint32_t x = wc[p];
+      const uint64_t t = wt[p];
+      // the triangle's edges other than {v,w}: {v,x} (contains v) and {w,x}
+      uint32_t evx = ND_NONE, ewx = ND_NONE;
+      for (int k = 0; k < 3; k++) {
+        const uint32_t z = te[3 * t + k];
+        if (z == e) continue;
+        if (eu[z] == v || ev[z] == v) evx = z;
+        else ewx = z;
+      }
+      uint64_t best = f - p - 1;   // W(vw) above x: the entries after p
+      uint32_t bsel = 0, boff = (uint32_t)(p + 1 - b);
+      const uint32_t lists[2] = {evx, ewx};
+      for (int k = 0; k < 2; k++) {
+        const uint64_t lb = wp[lists[k]], lf = wp[lists[k] + 1];
+        const uint64_t fst = upper_bound_u32(wc, lb, lf, x);
+        if (lf - fst < best) {
+          best = lf - fst;
+          bsel = (uint32_t)k + 1;
+          boff = (uint32_t)(fst - lb);
+        }
+      }
+      tlen[gi] = (uint32_t)best;
+      tsel[gi] = (bsel << 30) | boff;
+    }
+  }
+}
+
+// a vertex's (1,4) probe range must stay below 2^32 entries
+__global__ void k_t14_check(uint32_t n, const uint64_t *__restrict__ rp,
+                            const uint64_t *__restrict__ sg, const uint64_t *__restrict__ tg,
+                            uint32_t *status) {
+  for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n;
+       v += (uint64_t)gridDim.x * blockDim.x)
+    if (tg[sg[rp[v + 1]]] - tg[sg[rp[v]]] >= 0xFFFFFFFFull) atomicOr(status, ND_DERR_OVERFLOW);
+}
+
 // an edge's probe range must stay below 2^32 entries (32-bit work items)
 __global__ void k_w24_check(uint64_t m, const uint64_t *__restrict__ wp,
                             const uint64_t *__restrict__ wg, uint32_t *status) {
@@ -642,10 +702,12 @@ nd_status nd_stage_prep(nd_ctx *c, GraphView *gv) {
   gv->wt = nullptr;
   gv->te = nullptr;
 
-  const bool tri_tables = c->r == 3 || (c->r == 2 && c->s == 4) || (c->r == 1 && c->s == 3);
+  const bool tri_tables = c->r == 3 || (c->r == 2 && c->s == 4) || (c->r == 1 && c->s >= 3);
   gv->wg = nullptr;
   gv->wsel = nullptr;
   gv->sg = nullptr;
+  gv->tsel = nullptr;
+  gv->tg = nullptr;
   if (tri_tables && m) {
     uint32_t *sup = (uint32_t *)nd_buf(c, B_SUP, m * 4, &st);
     if (!sup) return st;
@@ -694,6 +756,26 @@ nd_status nd_stage_prep(nd_ctx *c, GraphView *gv) {
       st = nd_exclusive_scan_u32_to_u64(c, scnt, sgl, nnz, &total);
       if (st != ND_OK) return st;
       gv->sg = sgl;
+      if (c->s == 4) {
+        // (1,4): for every triangle probe (v, w, x) of (1,3), the probed part
+        // above x of W(vw), W(vx), W(wx), and the running sum of its length
+        const uint64_t ntp = total;   // triangle probes = 3 n_tri
+        uint32_t *tlen = (uint32_t *)nd_buf(c, B_W24L, std::max<uint64_t>(ntp, 1) * 4, &st);
+        if (!tlen) return st;
+        uint32_t *tsel = (uint32_t *)nd_buf(c, B_TSEL, std::max<uint64_t>(ntp, 1) * 4, &st);
+        if (!tsel) return st;
+        uint64_t *tg = (uint64_t *)nd_buf(c, B_TG, (ntp + 1) * 8, &st);
+        if (!tg) return st;
+        hipLaunchKernelGGL(k_t14_len, dim3(nd_grid(nnz, 256, 65536)), dim3(256), 0, c->stream,
+                           nnz, rp, col, eid, eu, ev, wp, wc, wt, te, sgl, tlen, tsel, n);
+        uint64_t t2 = 0;
+        st = nd_exclusive_scan_u32_to_u64(c, tlen, tg, ntp, &t2);
+        if (st != ND_OK) return st;
+        hipLaunchKernelGGL(k_t14_check, dim3(nd_grid(n, 256, 16384)), dim3(256), 0, c->stream, n,
+                           rp, sgl, tg, &sc->status);
+        gv->tsel = tsel;
+        gv->tg = tg;
+      }
     }
     if (c->r == 2) {
       // (2,4): probe length of every W entry's triangle, summed over all
@@ -722,12 +804,18 @@ nd_status nd_stage_prep(nd_ctx *c, GraphView *gv) {
     c->n_r = m;
   } else {
     c->n_r = n;
-    if (c->s == 3) {
-      // no edges: every vertex's triangle range is empty (sg = {0})
+    if (c->s >= 3) {
+      // no edges: every vertex's triangle range is empty (sg = tg = {0})
       uint64_t *sgl = (uint64_t *)nd_buf(c, B_SG, 8, &st);
       if (!sgl) return st;
       if ((st = nd_hip(c, hipMemsetAsync(sgl, 0, 8, c->stream), "sg")) != ND_OK) return st;
       gv->sg = sgl;
+      if (c->s == 4) {
+        uint64_t *tg = (uint64_t *)nd_buf(c, B_TG, 8, &st);
+        if (!tg) return st;
+        if ((st = nd_hip(c, hipMemsetAsync(tg, 0, 8, c->stream), "tg")) != ND_OK) return st;
+        gv->tg = tg;
+      }
     }
   }
   return nd_hip(c, hipGetLastError(), "prep kernels");

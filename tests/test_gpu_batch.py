@@ -52,6 +52,8 @@ def _degenerate():
         (I.batch_graph(3)[0], 2, 4),
         (I.batch_graph(5)[0], 1, 3),
         (I.two_k5_bridge(), 1, 3),
+        (I.batch_graph(7)[0], 1, 4),
+        (I.complete(7), 1, 4),
     ]
 
 
@@ -134,7 +136,7 @@ def test_batch_errors(ctx):
         ctx.decompose_batch([(ok, 2, 3), (bad, 2, 3)])
     assert e.value.code == nucleus.ND_E_BAD_GRAPH
     with pytest.raises(nucleus.NucleusError) as e:
-        ctx.decompose_batch([(ok, 1, 4)])
+        ctx.decompose_batch([(ok, 2, 5)])
     assert e.value.code == nucleus.ND_E_UNSUPPORTED
     with pytest.raises(nucleus.NucleusError) as e:
         ctx.decompose_batch([(ok, 3, 3)])

@@ -13,7 +13,7 @@ from paper_2306_08623_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-RS = [(1, 2), (2, 3), (3, 4), (2, 4), (1, 3)]
+RS = [(1, 2), (2, 3), (3, 4), (2, 4), (1, 3), (1, 4)]
 
 
 def _say(msg):
@@ -82,7 +82,7 @@ def test_er2k_workload(ctx, r, s):
     check(ctx, I.workload_er2k(), r, s, "er2k")
 
 
-@pytest.mark.parametrize("r,s", [(2, 3), (3, 4), (2, 4), (1, 3)])
+@pytest.mark.parametrize("r,s", [(2, 3), (3, 4), (2, 4), (1, 3), (1, 4)])
 def test_rmat_small(ctx, r, s):
     """Skewed degrees: R-MAT scale 12, edge factor 16."""
     check(ctx, I.rmat(12, 16, seed=7), r, s, "rmat12")
@@ -94,7 +94,7 @@ def test_schedule_invariance(ctx):
     interleaving)."""
     from paper_2306_08623_amd import nucleus
     g = I.er_planted(800, 0.02, 10, 6, 20, 5)
-    for r, s in [(2, 3), (3, 4), (2, 4), (1, 3)]:
+    for r, s in [(2, 3), (3, 4), (2, 4), (1, 3), (1, 4)]:
         d = oracle.decompose(g, r, s)
         for nb in (1, 3, 16, 64, 0):
             with nucleus.Context(device=0, peel_blocks=nb) as c2:

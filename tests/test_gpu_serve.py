@@ -25,7 +25,8 @@ def _requests(count=48, m_hi=40_000):
     reqs = [I.serve_graph(i, m_hi=m_hi) for i in range(count)]
     reqs[5:5] = [(I.empty(0), 2, 3), (I.complete(6), 3, 4), (I.empty(7), 1, 2),
                  (I.two_k5_bridge(), 2, 3), (I.complete(8), 2, 4),
-                 (I.serve_graph(1, m_hi=m_hi)[0], 2, 4), (I.serve_graph(2, m_hi=m_hi)[0], 1, 3)]
+                 (I.serve_graph(1, m_hi=m_hi)[0], 2, 4), (I.serve_graph(2, m_hi=m_hi)[0], 1, 3),
+                 (I.serve_graph(3, m_hi=m_hi)[0], 1, 4)]
     return reqs
 
 
@@ -126,7 +127,7 @@ def test_serve_errors():
     from paper_2306_08623_amd import nucleus
     with nucleus.Server(device=0) as srv:
         with pytest.raises(nucleus.NucleusError) as e:
-            srv.submit(I.complete(5), 1, 4)
+            srv.submit(I.complete(5), 2, 5)
         assert e.value.code == nucleus.ND_E_UNSUPPORTED
         bad = I.CSR(n=3, row_ptr=np.array([0, 1, 2, 2], np.uint64),
                     col=np.array([1, 3], np.uint32))
