@@ -86,8 +86,9 @@ typedef struct nd_options {
  *      number down (the paper's two-pass alternative, Section 7.4), with a
  *      union-find of partial trees that keeps each step independent of the
  *      depth of the hierarchy.
- * Neither flag: TE for (2,4), whose core numbers span thousands of levels
- * (Algorithm 5's link chains grow with them), EL for the other pairs. */
+ * Neither flag: TE when s - r >= 2 ((1,3), (1,4), (2,4)), whose core
+ * numbers span thousands of levels (Algorithm 5's link chains grow with
+ * them), EL for (1,2), (2,3), (3,4). */
 #define ND_FLAG_HIER_EL 2u
 #define ND_FLAG_HIER_TE 4u
 

@@ -302,8 +302,9 @@ enum BufId : int {
 };
 
 // hierarchy construction: Algorithm 5 during the peel ("EL"), or the
-// two-pass descending-core construction after it ("TE"); by default TE for
-// (2,4), whose core numbers span thousands of levels, EL otherwise
+// two-pass descending-core construction after it ("TE"); by default TE when
+// s - r >= 2 ((1,3), (1,4), (2,4): core numbers span thousands of levels),
+// EL otherwise
 inline bool nd_use_te(const nd_ctx *c);
 
 // the (r,s) pairs whose peel is built; index of a pair's batch slots
@@ -403,5 +404,5 @@ inline uint32_t nd_grid(uint64_t work, uint32_t block, uint32_t cap = 1u << 20) 
 inline bool nd_use_te(const nd_ctx *c) {
   if (c->flags & ND_FLAG_HIER_TE) return true;
   if (c->flags & ND_FLAG_HIER_EL) return false;
-  return c->r == 2 && c->s == 4;
+  return c->s - c->r >= 2;
 }
