@@ -101,6 +101,27 @@ def cpu_baseline(r: int, s: int, scale: int) -> dict:
     }
 
 
+def _oracle_batch_item(i: int) -> int:
+    import oracle
+    from paper_2306_08623_amd import inputs as I
+    g, r, s = I.batch_graph(i)
+    return oracle.decompose(g, r, s).n_s
+
+
+def cpu_batch_baseline(sample: int) -> dict:
+    """The oracle over the first `sample` graphs of the mixed batch, one
+    process per host core (graphs are independent), in graphs/s."""
+    import multiprocessing as mp
+    workers = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(workers) as pool:
+        pool.map(_oracle_batch_item, range(sample), chunksize=4)
+    dt = time.perf_counter() - t0
+    return {"value": sample / dt, "unit": "graphs/s", "cores": workers, "kind": "oracle",
+            "sample": f"full decompositions of batch graphs 0..{sample - 1}, {workers} processes, "
+                      f"{dt:.1f} s including process start and graph generation"}
+
+
 def bench_batch(count: int, reps: int) -> dict:
     """Batched vs one-by-one decomposition of the mixed batch, inputs
     resident in HBM, validation off in both (the inputs are validated once,
@@ -159,8 +180,12 @@ def bench_batch(count: int, reps: int) -> dict:
     torch.cuda.synchronize()
     t_one = time.perf_counter() - t1
     ctx.close()
+    cpu = cpu_batch_baseline(min(count, 512))
+    print(f"[bench] batch: oracle {cpu['value']:.1f} graphs/s on {cpu['cores']} processes",
+          file=sys.stderr, flush=True)
     return {
         "graphs": count,
+        "cpu_oracle": cpu,
         "workload": "inputs.batch_graph(i, 4000000), i < %d: n log-uniform in [64, 65536], "
                     "Erdos-Renyi (avg degree 8) or Chung-Lu (exponent 2.3) + 1..10 planted "
                     "cliques of size 6..24, (2,3)/(3,4) alternating in pairs" % count,
