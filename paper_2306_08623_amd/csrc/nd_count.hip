@@ -143,50 +143,49 @@ __global__ void __launch_bounds__(kCountBlock) k_count_s4(GraphView g, uint32_t 
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    // pairs {cv[a], cv[b]}, a < b
-    for (uint32_t a = 0; a + 1 < c; a++) {
-      const uint32_t w = cv[a];
-      const uint64_t kw = g.okey[w];
-      uint32_t hits_a = 0;   // r = 3: 4-cliques through triangle {u, v, w}
-      for (uint32_t b = a + 1 + lane; b < c; b += 64) {
-        const uint32_t x = cv[b];
-        // adjacency of w and x through the out-row of the lower-key vertex
-        uint32_t lowv = w, highv = x;
-        if (g.okey[x] < kw) { lowv = x; highv = w; }
-        const uint64_t bl = g.dgp[lowv], el = g.dgp[lowv + 1];
-        const uint64_t p = find_u32<uint64_t>(g.dgc, bl, el, highv);
-        if (p == el) continue;
-        local++;
-        if (R == 1) {
-          atomicAdd(&cnt[u], 1u);
-          atomicAdd(&cnt[v], 1u);
-          atomicAdd(&cnt[w], 1u);
-          atomicAdd(&cnt[x], 1u);
-        } else if (R == 2) {
-          atomicAdd(&cnt[e_uv], 1u);
-          atomicAdd(&cnt[ceu[a]], 1u);
-          atomicAdd(&cnt[cev[a]], 1u);
-          atomicAdd(&cnt[ceu[b]], 1u);
-          atomicAdd(&cnt[cev[b]], 1u);
-          atomicAdd(&cnt[g.dge[p]], 1u);
-        } else {
-          // triangles {u,v,w} and {u,v,x} are counted per C2 entry (LDS),
-          // {u,w,x} and {v,w,x} per 4-clique
-          const uint32_t e_wx = g.dge[p];
-          hits_a++;
-          atomicAdd(&cn[b % TC], 1u);
-          const uint32_t t2[2] = {tri_lookup(g, u, w, x, ceu[a], ceu[b], e_wx),
-                                  tri_lookup(g, v, w, x, cev[a], cev[b], e_wx)};
-#pragma unroll
-          for (int z = 0; z < 2; z++) {
-            if (t2[z] == ND_NONE) atomicOr(&sc->status, ND_DERR_BADGRAPH);
-            else atomicAdd(&cnt[t2[z]], 1u);
-          }
-        }
+    // pairs {cv[a], cv[b]}, a < b, all c(c-1)/2 of them spread over the
+    // lanes: lane l takes pair numbers l, l + 64, ... in row-major order
+    const uint64_t npairs = (uint64_t)c * (c - 1) / 2;
+    uint32_t a = 0, b = 1 + lane;
+    for (uint64_t q = lane; q < npairs; q += 64, b += 64) {
+      while (b >= c) {   // next row: row a + 1 starts at b = a + 2
+        const uint32_t over = b - c;
+        a++;
+        b = a + 1 + over;
       }
-      if (R == 3) {
-        hits_a = wave_sum64(hits_a);
-        if (lane == 0 && hits_a) atomicAdd(&cn[a % TC], hits_a);
+      const uint32_t w = cv[a], x = cv[b];
+      // adjacency of w and x through the out-row of the lower-key vertex
+      uint32_t lowv = w, highv = x;
+      if (g.okey[x] < g.okey[w]) { lowv = x; highv = w; }
+      const uint64_t bl = g.dgp[lowv], el = g.dgp[lowv + 1];
+      const uint64_t p = find_u32<uint64_t>(g.dgc, bl, el, highv);
+      if (p == el) continue;
+      local++;
+      if (R == 1) {
+        atomicAdd(&cnt[u], 1u);
+        atomicAdd(&cnt[v], 1u);
+        atomicAdd(&cnt[w], 1u);
+        atomicAdd(&cnt[x], 1u);
+      } else if (R == 2) {
+        atomicAdd(&cnt[e_uv], 1u);
+        atomicAdd(&cnt[ceu[a]], 1u);
+        atomicAdd(&cnt[cev[a]], 1u);
+        atomicAdd(&cnt[ceu[b]], 1u);
+        atomicAdd(&cnt[cev[b]], 1u);
+        atomicAdd(&cnt[g.dge[p]], 1u);
+      } else {
+        // triangles {u,v,w} and {u,v,x} are counted per C2 entry (LDS),
+        // {u,w,x} and {v,w,x} per 4-clique
+        const uint32_t e_wx = g.dge[p];
+        atomicAdd(&cn[a % TC], 1u);
+        atomicAdd(&cn[b % TC], 1u);
+        const uint32_t t2[2] = {tri_lookup(g, u, w, x, ceu[a], ceu[b], e_wx),
+                                tri_lookup(g, v, w, x, cev[a], cev[b], e_wx)};
+#pragma unroll
+        for (int z = 0; z < 2; z++) {
+          if (t2[z] == ND_NONE) atomicOr(&sc->status, ND_DERR_BADGRAPH);
+          else atomicAdd(&cnt[t2[z]], 1u);
+        }
       }
     }
     if (R == 3) {
