@@ -104,7 +104,7 @@ nd_status nd_coop_launch(nd_ctx *c, const void *kern, uint32_t *nb, uint32_t *nb
   DevScalars *sc = (DevScalars *)c->bufs[B_SCAL].p;
   for (;;) {
     *nb_arg = *nb;
-    nd_status st = nd_hip(c, hipMemsetAsync(&sc->barrier, 0, 8, c->stream), "barrier reset");
+    nd_status st = nd_hip(c, hipMemsetAsync(sc->bar, 0, sizeof(sc->bar), c->stream), "barrier reset");
     if (st != ND_OK) return st;
     if (before) (void)hipEventRecord(before, c->stream);
     st = nd_hip(c, hipLaunchCooperativeKernel(kern, dim3(*nb), block, args, 0, c->stream), what);

@@ -78,7 +78,8 @@ __device__ __forceinline__ uint64_t upper_bound_u32(const uint32_t *a, uint64_t 
 }
 
 // Coherent (agent-scope) relaxed atomics. Plain loads may hit a stale line in
-// another XCD's L2; these go to the coherence point.
+// another XCD's L2; these go to the coherence point. (Relaxed: no cache
+// invalidation; ordering comes from fences where it is needed.)
 __device__ __forceinline__ uint32_t ld_acq32(const uint32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -169,22 +170,51 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t *counter, bool want) {
 // 20 s at the 100 MHz real-time counter: far beyond any legitimate wait.
 constexpr uint64_t kBarrierTimeoutTicks = 2000000000ull;
 
-// Grid-wide barrier for a persistent launch whose blocks are all resident
-// (cooperative launch). `bar` counts arrivals monotonically; a block waits
-// until every block of this generation arrived. The fences make every
-// global write before the barrier visible to every read after it across
-// XCDs. A watchdog bound turns a stuck wait into an error flag instead of a
-// hang: once `status` is non-zero every waiter leaves.
+// Grid-wide barrier state of a persistent launch, in 64-bit words: the
+// release generation, the count of groups done, the residency gate's
+// arrivals, then one arrival counter per group of workgroups, each word on
+// a 128-byte line of its own. All words start at zero for every launch.
+constexpr uint32_t kBarGroups = 8;     // workgroup b is in group b % 8
+constexpr uint32_t kBarLine = 16;      // 64-bit words per 128-byte line
+constexpr uint32_t kBarRelease = 0;
+constexpr uint32_t kBarDone = kBarLine;
+constexpr uint32_t kBarGate = 2 * kBarLine;
+constexpr uint32_t kBarGroup0 = 3 * kBarLine;
+constexpr uint32_t kBarWords = kBarGroup0 + kBarGroups * kBarLine;
+
+// Grid-wide barrier for a persistent launch whose workgroups are all
+// resident (cooperative launch). Arrivals are counted per group (monotone
+// counters: a workgroup's generation is its arrival index over the group's
+// size); the last arrival of a group counts the group done, and the last
+// group publishes the generation, which every workgroup waits for. Fences:
+// release before the arrival, acquire after the wait (one each per
+// workgroup: an agent-scope fence writes back or invalidates the caches, so
+// none is taken inside the wait loop); the last arrivals, which carry the
+// other workgroups' arrivals on, take both. A watchdog bound turns a stuck
+// wait into an error flag instead of a hang: once `status` is non-zero
+// every waiter leaves.
 __device__ __forceinline__ bool grid_barrier(uint64_t *bar, uint32_t nblocks, uint32_t *status) {
   __syncthreads();
   __shared__ uint32_t s_ok;
   if (threadIdx.x == 0) {
-    __threadfence();
-    uint64_t arrived = atomicAdd((unsigned long long *)bar, 1ull);
-    uint64_t target = (arrived / nblocks + 1) * (uint64_t)nblocks;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const uint32_t ng = nblocks < kBarGroups ? nblocks : kBarGroups;
+    const uint32_t grp = blockIdx.x % ng;
+    const uint32_t gsize = nblocks / ng + (grp < nblocks % ng ? 1u : 0u);
+    const uint64_t arrived =
+        atomicAdd((unsigned long long *)(bar + kBarGroup0 + kBarLine * grp), 1ull);
+    const uint64_t gen = arrived / gsize + 1;
+    if (arrived % gsize == gsize - 1) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+      const uint64_t done = atomicAdd((unsigned long long *)(bar + kBarDone), 1ull);
+      if (done % ng == ng - 1) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        __hip_atomic_store(bar + kBarRelease, gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
     uint32_t ok = 1;
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();   // 100 MHz clock
-    while (ld_acq64(bar) < target) {
+    while (ld_acq64(bar + kBarRelease) < gen) {
       if (ld_acq32(status) != 0) { ok = 0; break; }
       if (__builtin_amdgcn_s_memrealtime() - t0 > kBarrierTimeoutTicks) {
         atomicOr(status, ND_DERR_WATCHDOG);
@@ -193,7 +223,7 @@ __device__ __forceinline__ bool grid_barrier(uint64_t *bar, uint32_t nblocks, ui
       }
       __builtin_amdgcn_s_sleep(1);
     }
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     s_ok = ok;
   }
   __syncthreads();
@@ -212,10 +242,10 @@ __device__ __forceinline__ bool residency_gate(uint64_t *bar, uint32_t nblocks,
   __syncthreads();
   __shared__ uint32_t s_in;
   if (threadIdx.x == 0) {
-    atomicAdd((unsigned long long *)bar, 1ull);
+    atomicAdd((unsigned long long *)(bar + kBarGate), 1ull);
     uint32_t ok = 1;
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-    while (ld_acq64(bar) < (uint64_t)nblocks) {
+    while (ld_acq64(bar + kBarGate) < (uint64_t)nblocks) {
       if (ld_acq32(status) != 0) { ok = 0; break; }
       if (__builtin_amdgcn_s_memrealtime() - t0 > kResidencyTicks) {
         atomicOr(status, ND_DERR_RESIDENCY);
@@ -224,7 +254,7 @@ __device__ __forceinline__ bool residency_gate(uint64_t *bar, uint32_t nblocks,
       }
       __builtin_amdgcn_s_sleep(1);
     }
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     s_in = ok;
   }
   __syncthreads();
@@ -327,7 +357,6 @@ inline int nd_batch_slot(int group, int field) { return B_COUNT + group * kBatch
 // device scalars block (one per context)
 struct DevScalars {
   uint64_t n_s;            // s-cliques counted
-  uint64_t barrier;        // grid barrier arrivals
   uint64_t visits, decrements, links, unites;
   uint64_t bucket_scans;
   uint64_t link_calls;     // link calls issued after the redundancy filter
@@ -343,6 +372,7 @@ struct DevScalars {
   uint32_t orient_round;
   uint32_t n_kept;         // tree: kept nodes
   uint32_t pad[5];
+  alignas(128) uint64_t bar[kBarWords];   // grid barrier state (zeroed before each launch)
 };
 
 // helpers implemented in nd_api.hip

@@ -660,7 +660,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
   lc.unites = 0;
   uint64_t visits = 0, decs = 0, scans = 0, calls = 0;
   for (uint32_t i = threadIdx.x; i < kLinkCache; i += kPeelBlock) s_lcache[i] = ~0ull;
-  if (!residency_gate(&sc->barrier, nb, &sc->status)) return;
+  if (!residency_gate(sc->bar, nb, &sc->status)) return;
 
   uint32_t k = 0;
   uint32_t t = 0;
@@ -727,7 +727,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
         a.acnt[(qp ^ 1) * nb + blockIdx.x] = nkeep;
         if (nkeep) atomicAdd(&sc->n_alive[qp ^ 1], nkeep);
       }
-      if (!grid_barrier(&sc->barrier, nb, &sc->status)) break;
+      if (!grid_barrier(sc->bar, nb, &sc->status)) break;
       const uint32_t nout = ld_acq32(&sc->n_alive[qp ^ 1]);
       if (nout == 0) {
         done = true;
@@ -752,7 +752,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
       scans++;
       nscan++;
       k = kq;
-      if (!grid_barrier(&sc->barrier, nb, &sc->status)) break;
+      if (!grid_barrier(sc->bar, nb, &sc->status)) break;
       f = ld_acq32(&sc->fsize[t & 1]);
     }
 
@@ -793,7 +793,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
     }
     if (threadIdx.x == 0) a.btot[blockIdx.x] = run;
     if (gtid == 0) sc->fsize[(t + 1) & 1] = 0;
-    if (!grid_barrier(&sc->barrier, nb, &sc->status)) break;
+    if (!grid_barrier(sc->bar, nb, &sc->status)) break;
 
     // ---- visit: one probe element per lane over the whole frontier
     {
@@ -920,7 +920,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
       }
     }
     if (kLink) wave_q_drain(lc, wq, qn, 1);
-    if (!grid_barrier(&sc->barrier, nb, &sc->status)) break;
+    if (!grid_barrier(sc->bar, nb, &sc->status)) break;
 
     // ---- drain spilled link pairs (rare): repeat until the queue is empty
     bool ok = true;
@@ -936,9 +936,9 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
         const uint64_t slot = (h + (uint32_t)d) & (a.linkq_cap - 1);
         link_efficient(lc, a.linkq[2 * slot], a.linkq[2 * slot + 1]);
       }
-      if (!grid_barrier(&sc->barrier, nb, &sc->status)) { ok = false; break; }
+      if (!grid_barrier(sc->bar, nb, &sc->status)) { ok = false; break; }
       if (gtid == 0) sc->linkq_head = tl;
-      if (!grid_barrier(&sc->barrier, nb, &sc->status)) { ok = false; break; }
+      if (!grid_barrier(sc->bar, nb, &sc->status)) { ok = false; break; }
     }
     if (!ok) break;
     t++;
@@ -1035,7 +1035,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_hier(HierArgs a) {
   const uint64_t gtid = blockIdx.x * (uint64_t)kPeelBlock + threadIdx.x;
   const uint64_t nthreads = (uint64_t)nb * kPeelBlock;
   uint64_t visits = 0, pairs = 0, unites = 0;
-  if (!residency_gate(&sc->barrier, nb, &sc->status)) return;
+  if (!residency_gate(sc->bar, nb, &sc->status)) return;
 
   for (uint32_t c = a.k; c >= 1; c--) {
     const uint64_t fb = a.loff[a.k - c], fe = a.loff[a.k - c + 1];
@@ -1069,7 +1069,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_hier(HierArgs a) {
       __syncthreads();
     }
     if (threadIdx.x == 0) a.btot[blockIdx.x] = run;
-    if (!grid_barrier(&sc->barrier, nb, &sc->status)) break;
+    if (!grid_barrier(sc->bar, nb, &sc->status)) break;
     {
       const uint32_t per = (nb + kPeelBlock - 1) / kPeelBlock;
       const uint32_t j0 = threadIdx.x * per;
@@ -1121,7 +1121,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_hier(HierArgs a) {
         }
       }
     }
-    if (!grid_barrier(&sc->barrier, nb, &sc->status)) break;
+    if (!grid_barrier(sc->bar, nb, &sc->status)) break;
   }
   const uint64_t v = wave_sum64(visits), l = wave_sum64(pairs), u = wave_sum64(unites);
   if (lane == 0) {
@@ -1304,12 +1304,12 @@ nd_status nd_stage_peel(nd_ctx *c, const GraphView &g) {
     return st;
   if ((st = nd_hip(c, hipMemsetAsync(pa.L, 0xFF, nr * 4, c->stream), "L")) != ND_OK) return st;
   hipLaunchKernelGGL(k_iota, dim3(nd_grid(nr, 256, 16384)), dim3(256), 0, c->stream, pa.uf, nr);
-  // scalars: counters zero, kmin = NONE, barrier zero
+  // scalars: counters zero, kmin = NONE (the barrier words are cleared per launch)
   DevScalars init;
   memset(&init, 0, sizeof(init));
   init.kmin[0] = init.kmin[1] = ND_NONE;
   // keep n_s and max_outdeg: copy only the fields the peel owns
-  const size_t off_lo = offsetof(DevScalars, barrier);
+  const size_t off_lo = offsetof(DevScalars, visits);
   const size_t off_hi = offsetof(DevScalars, max_outdeg);
   if ((st = nd_hip(c,
                    hipMemcpyAsync((char *)sc + off_lo, (char *)&init + off_lo, off_hi - off_lo,

@@ -205,7 +205,7 @@ __global__ void __launch_bounds__(kOrientBlock) k_orient(OrientArgs a) {
   __shared__ uint64_t s_left[kOrientBlock / 64], s_sum[kOrientBlock / 64];
   const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t nth = gridDim.x * blockDim.x;
-  if (!residency_gate(&a.sc->barrier, a.nblocks, &a.sc->status)) return;
+  if (!residency_gate(a.sc->bar, a.nblocks, &a.sc->status)) return;
   for (uint32_t round = 0;; round++) {
     uint64_t *cur = a.sums + 2 * (round & 1);
     uint64_t *nxt = a.sums + 2 * ((round + 1) & 1);
@@ -237,7 +237,7 @@ __global__ void __launch_bounds__(kOrientBlock) k_orient(OrientArgs a) {
         nxt[1] = 0;
       }
     }
-    if (!grid_barrier(&a.sc->barrier, a.nblocks, &a.sc->status)) return;
+    if (!grid_barrier(a.sc->bar, a.nblocks, &a.sc->status)) return;
     const uint64_t L = ld_acq64(&cur[0]);
     const uint64_t S = ld_acq64(&cur[1]);
     if (L == 0) {
@@ -249,7 +249,7 @@ __global__ void __launch_bounds__(kOrientBlock) k_orient(OrientArgs a) {
     for (uint32_t v = tid; v < a.n; v += nth) {
       if (a.orank[v] == ND_NONE && (last || 2ull * a.rdeg[v] * L <= 3ull * S)) a.orank[v] = round;
     }
-    if (!grid_barrier(&a.sc->barrier, a.nblocks, &a.sc->status)) return;
+    if (!grid_barrier(a.sc->bar, a.nblocks, &a.sc->status)) return;
     // phase 3: removed vertices lower their remaining neighbours' degrees
     for (uint32_t v = tid; v < a.n; v += nth) {
       if (a.orank[v] != round) continue;
@@ -258,7 +258,7 @@ __global__ void __launch_bounds__(kOrientBlock) k_orient(OrientArgs a) {
         if (a.orank[w] == ND_NONE) atomicSub(&a.rdeg[w], 1u);
       }
     }
-    if (!grid_barrier(&a.sc->barrier, a.nblocks, &a.sc->status)) return;
+    if (!grid_barrier(a.sc->bar, a.nblocks, &a.sc->status)) return;
   }
 }
 
@@ -654,8 +654,6 @@ nd_status nd_stage_prep(nd_ctx *c, GraphView *gv) {
                 "copy deg");
     if (st != ND_OK) return st;
     st = nd_hip(c, hipMemsetAsync(sums, 0, 64, c->stream), "memset sums");
-    if (st != ND_OK) return st;
-    st = nd_hip(c, hipMemsetAsync(&sc->barrier, 0, 8, c->stream), "memset barrier");
     if (st != ND_OK) return st;
     OrientArgs oa{};
     oa.n = n;
