@@ -39,6 +39,7 @@ namespace {
 
 constexpr uint32_t kPeelBlock = 256;
 constexpr uint32_t kMaxPeelBlocks = 2048;
+constexpr uint32_t kScanU = 4;   // bucket scan: entries per thread and pass
 constexpr uint32_t kLocalStack = 8;
 constexpr uint32_t kLinkStepCap = 1u << 24;
 
@@ -637,6 +638,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
   __shared__ uint64_t s_boff[kMaxPeelBlocks + 1];
   __shared__ uint32_t s_red[kPeelBlock / 64];
   __shared__ uint32_t s_cnt[kPeelBlock / 64];
+  __shared__ uint32_t s_bmin;   // this workgroup's minimum at the last bucket scan
   __shared__ uint64_t s_red64[kPeelBlock / 64];
   __shared__ uint64_t s_lcache[kLinkCache];
   __shared__ uint64_t s_lq[kLink ? kPeelBlock / 64 : 1][kLink ? kWaveQ : 1];
@@ -688,32 +690,39 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
       uint32_t *out = (qp ? a.al0 : a.al1) + rbeg;
       const uint32_t nin = (nscan == 0) ? (uint32_t)(min64(rbeg + bseg, a.n_r) - rbeg)
                                         : a.acnt[qp * nb + blockIdx.x];
+      // each thread takes kScanU consecutive entries per pass (more loads in
+      // flight); a block-wide exclusive scan of the kept counts preserves order
       uint32_t mn = ND_NONE;
       uint32_t nkeep = 0;
-      for (uint32_t base = 0; base < nin; base += kPeelBlock) {
-        const uint32_t i = base + threadIdx.x;
-        bool keep = false;
-        uint32_t id = 0;
-        if (i < nin) {
-          id = (nscan == 0) ? (uint32_t)(rbeg + i) : in[i];
-          if (a.round[id] == ND_ALIVE) {
-            keep = true;
-            uint32_t cv = a.cnt[id];
+      for (uint32_t base = 0; base < nin; base += kPeelBlock * kScanU) {
+        const uint32_t i0 = base + threadIdx.x * kScanU;
+        uint32_t id[kScanU], rv[kScanU];
+#pragma unroll
+        for (uint32_t u = 0; u < kScanU; u++)
+          id[u] = (i0 + u < nin) ? ((nscan == 0) ? (uint32_t)(rbeg + i0 + u) : in[i0 + u]) : 0;
+#pragma unroll
+        for (uint32_t u = 0; u < kScanU; u++) rv[u] = (i0 + u < nin) ? a.round[id[u]] : 0;
+        uint32_t nk = 0;
+#pragma unroll
+        for (uint32_t u = 0; u < kScanU; u++) {
+          if (i0 + u < nin && rv[u] == ND_ALIVE) {
+            const uint32_t cv = a.cnt[id[u]];
             mn = cv < mn ? cv : mn;
+            nk++;
           }
         }
-        const uint64_t m = ballot64(keep);
-        if (lane == 0) s_cnt[wv] = __popcll(m);
+        const uint32_t incl = wave_incl_scan(nk);
+        if (lane == 63) s_cnt[wv] = incl;
         __syncthreads();
         uint32_t woff = 0, tot = 0;
         for (uint32_t w = 0; w < kPeelBlock / 64; w++) {
           woff += w < wv ? s_cnt[w] : 0;
           tot += s_cnt[w];
         }
-        if (keep) {
-          const uint64_t below = m & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)));
-          out[nkeep + woff + __popcll(below)] = id;
-        }
+        uint32_t o = nkeep + woff + incl - nk;
+#pragma unroll
+        for (uint32_t u = 0; u < kScanU; u++)
+          if (i0 + u < nin && rv[u] == ND_ALIVE) out[o++] = id[u];
         nkeep += tot;
         __syncthreads();
       }
@@ -726,6 +735,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
         if (bm != ND_NONE) atomicMin(&sc->kmin[qp], bm);
         a.acnt[(qp ^ 1) * nb + blockIdx.x] = nkeep;
         if (nkeep) atomicAdd(&sc->n_alive[qp ^ 1], nkeep);
+        s_bmin = bm;
       }
       if (!grid_barrier(sc->bar, nb, &sc->status)) break;
       const uint32_t nout = ld_acq32(&sc->n_alive[qp ^ 1]);
@@ -738,16 +748,30 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
         sc->n_alive[qp] = 0;         // becomes the total of the next scan
         sc->kmin[qp ^ 1] = ND_NONE;  // minimum of the next scan
       }
-      for (uint32_t base = 0; base < nkeep; base += kPeelBlock) {
-        const uint32_t i = base + threadIdx.x;
-        bool take = false;
-        uint32_t id = 0;
-        if (i < nkeep) {
-          id = out[i];
-          take = a.cnt[id] == kq;
+      // the new frontier: entries at the new level (none in a segment whose
+      // minimum is above it)
+      if (s_bmin == kq) {
+        for (uint32_t base = 0; base < nkeep; base += kPeelBlock * kScanU) {
+          const uint32_t i0 = base + threadIdx.x * kScanU;
+          uint32_t id[kScanU];
+#pragma unroll
+          for (uint32_t u = 0; u < kScanU; u++) id[u] = (i0 + u < nkeep) ? out[i0 + u] : 0;
+          bool take[kScanU];
+          uint32_t nt = 0;
+#pragma unroll
+          for (uint32_t u = 0; u < kScanU; u++) {
+            take[u] = i0 + u < nkeep && a.cnt[id[u]] == kq;
+            nt += take[u];
+          }
+          const uint32_t incl = wave_incl_scan(nt);
+          uint32_t wbase = 0;
+          if (lane == 63 && incl) wbase = atomicAdd(&sc->fsize[t & 1], incl);
+          wbase = __shfl(wbase, 63, 64);
+          uint32_t o = wbase + incl - nt;
+#pragma unroll
+          for (uint32_t u = 0; u < kScanU; u++)
+            if (take[u]) F[o++] = id[u];
         }
-        uint32_t slot = wave_append(&sc->fsize[t & 1], take);
-        if (take) F[slot] = id;
       }
       scans++;
       nscan++;
