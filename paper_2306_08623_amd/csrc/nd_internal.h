@@ -327,7 +327,7 @@ enum BufId : int {
   B_SCAL, B_TMP64, B_TMP32A, B_TMP32B, B_TMP32C, B_TMP32D,
   B_SORTK0, B_SORTK1, B_SORTV0, B_SORTV1, B_HIST,
   B_PARENT, B_LEVEL, B_RCL, B_GCACHE, B_ACNT, B_NODEML, B_SORTOFF,
-  B_BATCHDESC, B_WG, B_W24L, B_LHIST, B_LOFF, B_SG, B_TSEL, B_TG,
+  B_BATCHDESC, B_WG, B_W24L, B_LHIST, B_LOFF, B_SG, B_TSEL, B_TG, B_PSTATE,
   B_COUNT
 };
 

@@ -40,6 +40,9 @@ namespace {
 constexpr uint32_t kPeelBlock = 256;
 constexpr uint32_t kMaxPeelBlocks = 2048;
 constexpr uint32_t kScanU = 4;   // bucket scan: entries per thread and pass
+// Peel state of an r-clique as the visits of a round read it: all they need
+// of the round number, in a byte (a quarter of the lines of the round array)
+constexpr uint8_t kAlive = 0, kPeeledNow = 1, kPeeledBefore = 2;
 constexpr uint32_t kLocalStack = 8;
 constexpr uint32_t kLinkStepCap = 1u << 24;
 
@@ -48,6 +51,7 @@ struct PeelArgs {
   uint64_t n_r;
   uint32_t *cnt;      // s-clique count; the core number once peeled
   uint32_t *round;    // peel round, ND_ALIVE while present
+  uint8_t *pst;       // peel state: kAlive, kPeeledNow (this round), kPeeledBefore
   uint32_t *uf;       // union-find parent
   uint32_t *L;        // nearest lower core link of a uf root
   uint32_t *F0, *F1;  // frontiers by round parity
@@ -667,6 +671,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
   uint32_t k = 0;
   uint32_t t = 0;
   uint32_t nscan = 0;   // bucket scans done
+  uint32_t fprev = 0;   // frontier size of the previous round
   bool done = false;
 
   while (!done) {
@@ -701,11 +706,11 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
         for (uint32_t u = 0; u < kScanU; u++)
           id[u] = (i0 + u < nin) ? ((nscan == 0) ? (uint32_t)(rbeg + i0 + u) : in[i0 + u]) : 0;
 #pragma unroll
-        for (uint32_t u = 0; u < kScanU; u++) rv[u] = (i0 + u < nin) ? a.round[id[u]] : 0;
+        for (uint32_t u = 0; u < kScanU; u++) rv[u] = (i0 + u < nin) ? a.pst[id[u]] : kPeeledBefore;
         uint32_t nk = 0;
 #pragma unroll
         for (uint32_t u = 0; u < kScanU; u++) {
-          if (i0 + u < nin && rv[u] == ND_ALIVE) {
+          if (i0 + u < nin && rv[u] == kAlive) {
             const uint32_t cv = a.cnt[id[u]];
             mn = cv < mn ? cv : mn;
             nk++;
@@ -722,7 +727,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
         uint32_t o = nkeep + woff + incl - nk;
 #pragma unroll
         for (uint32_t u = 0; u < kScanU; u++)
-          if (i0 + u < nin && rv[u] == ND_ALIVE) out[o++] = id[u];
+          if (i0 + u < nin && rv[u] == kAlive) out[o++] = id[u];
         nkeep += tot;
         __syncthreads();
       }
@@ -792,6 +797,10 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
     const uint64_t seg = (f + nb - 1) / nb;
     const uint64_t sbeg = min64((uint64_t)blockIdx.x * seg, f);
     const uint64_t send = min64(sbeg + seg, f);
+    // the previous round's frontier (in Fn, which takes pushes only after the
+    // barrier below) becomes peeled-before
+    for (uint64_t i = gtid; i < fprev; i += nthreads) a.pst[Fn[i]] = kPeeledBefore;
+    fprev = f;
     uint64_t run = 0;
     for (uint64_t base = sbeg; base < send; base += kPeelBlock) {
       const uint64_t i = base + threadIdx.x;
@@ -799,6 +808,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
       if (i < send) {
         const uint32_t R = F[i];
         a.round[R] = t;
+        a.pst[R] = kPeeledNow;
         a.cnt[R] = k;
         w = Sh::len(g, R);
       }
@@ -888,18 +898,18 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
         const uint32_t idx = (uint32_t)(qoff - before);
         if (Sh::visit(g, R, idx, others)) {
           visits++;
-          uint32_t rr[NO];
+          uint32_t rr[NO];   // peel states
           bool dead = false, lead = true;
 #pragma unroll
           for (int j = 0; j < NO; j++) {
-            rr[j] = a.round[others[j]];
-            dead |= rr[j] < t;
-            lead &= !(rr[j] == t && others[j] < R);
+            rr[j] = a.pst[others[j]];
+            dead |= rr[j] == kPeeledBefore;
+            lead &= !(rr[j] == kPeeledNow && others[j] < R);
           }
           if (!dead && lead) {
 #pragma unroll
             for (int j = 0; j < NO; j++) {
-              if (rr[j] == ND_ALIVE) {
+              if (rr[j] == kAlive) {
                 uint32_t old = atomicSub(&a.cnt[others[j]], 1u);
                 decs++;
                 push[j] = (old == k + 1);
@@ -909,7 +919,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_peel(PeelArgs a) {
           uint32_t qroot = ND_NONE;   // cache key of R's set, formed on first use
 #pragma unroll
           for (int j = 0; j < NO; j++) {
-            if (kLink && (rr[j] < t || (rr[j] == t && R < others[j]))) {
+            if (kLink && (rr[j] == kPeeledBefore || (rr[j] == kPeeledNow && R < others[j]))) {
               if (qroot == ND_NONE) qroot = key_root(a.uf, R);
               const uint32_t x = key_root(a.uf, others[j]);
               if (x == qroot || lcache_hit(s_lcache, x, qroot)) continue;
@@ -1297,6 +1307,7 @@ nd_status nd_stage_peel(nd_ctx *c, const GraphView &g) {
   pa.n_r = nr;
   pa.cnt = (uint32_t *)c->bufs[B_CNT].p;
   if (!(pa.round = (uint32_t *)nd_buf(c, B_ROUND, nr * 4, &st))) return st;
+  if (!(pa.pst = (uint8_t *)nd_buf(c, B_PSTATE, nr, &st))) return st;
   if (!(pa.uf = (uint32_t *)nd_buf(c, B_UF, nr * 4, &st))) return st;
   if (!(pa.L = (uint32_t *)nd_buf(c, B_L, nr * 4, &st))) return st;
   if (!(pa.F0 = (uint32_t *)nd_buf(c, B_F0, nr * 4, &st))) return st;
@@ -1325,6 +1336,8 @@ nd_status nd_stage_peel(nd_ctx *c, const GraphView &g) {
   pa.max_rounds = (uint32_t)std::min<uint64_t>(wd, 0xFFFFFFF0ull);
 
   if ((st = nd_hip(c, hipMemsetAsync(pa.round, 0xFF, nr * 4, c->stream), "round")) != ND_OK)
+    return st;
+  if ((st = nd_hip(c, hipMemsetAsync(pa.pst, kAlive, nr, c->stream), "peel state")) != ND_OK)
     return st;
   if ((st = nd_hip(c, hipMemsetAsync(pa.L, 0xFF, nr * 4, c->stream), "L")) != ND_OK) return st;
   hipLaunchKernelGGL(k_iota, dim3(nd_grid(nr, 256, 16384)), dim3(256), 0, c->stream, pa.uf, nr);

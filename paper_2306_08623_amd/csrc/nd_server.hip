@@ -65,7 +65,7 @@ void estimate(uint32_t n, uint64_t nnz, const uint64_t *rp, const uint32_t *col,
     tri = sum / 3;
   }
   const uint64_t n_r = r == 1 ? n : (r == 2 ? m : tri);
-  uint64_t w = 56ull * (n + 1) + 32ull * m + (150ull + 8ull * r) * n_r + 64;
+  uint64_t w = 56ull * (n + 1) + 32ull * m + (151ull + 8ull * r) * n_r + 64;
   if (s >= 3) w += 24ull * (m + 1) + 36ull * tri;
   if (r == 2 && s == 4) w += 48ull * tri;   // probe parts, lengths, running sums
   if (r == 1 && s >= 3) w += 24ull * (m + 1);   // per-slot triangle counts and sums
