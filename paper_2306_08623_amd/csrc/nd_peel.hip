@@ -636,7 +636,7 @@ __device__ __forceinline__ uint32_t key_root(const uint32_t *uf, uint32_t x) {
 // ---------------------------------------------------------------------------
 
 template <int R_, int S_, bool kLink>
-__global__ void __launch_bounds__(kPeelBlock, 4) k_peel(PeelArgs a) {
+__global__ void __launch_bounds__(kPeelBlock, 5) k_peel(PeelArgs a) {
   using Sh = Shape<R_, S_>;
   constexpr int NO = Sh::kOthers;
   __shared__ uint64_t s_boff[kMaxPeelBlocks + 1];
