@@ -23,7 +23,7 @@
 namespace {
 
 constexpr uint32_t kCountBlock = 256;
-constexpr uint32_t kC2Cap = 1024;   // LDS capacity per wave for C2 (entries)
+constexpr uint32_t kC2Cap = 1024;   // largest C2 (and oriented out-degree) the 4-clique kernel takes
 
 __global__ void k_count_degree(uint32_t n, const uint64_t *__restrict__ rp,
                                uint32_t *__restrict__ cnt) {
@@ -82,26 +82,26 @@ __global__ void __launch_bounds__(kCountBlock) k_count_s3(GraphView g, uint32_t 
   if (lane_id() == 0 && local) atomicAdd((unsigned long long *)&sc->n_s, (unsigned long long)local);
 }
 
+// LDS arrays of `cap` entries per wave: C2 vertices, their edge ids to u and
+// to v, and for r = 3 the triangle {u, v, w} of each entry and the 4-cliques
+// found so far through it
+template <int R>
+constexpr uint32_t count_s4_arrays() { return R == 3 ? 5 : 3; }
+
 template <int R>
 __global__ void __launch_bounds__(kCountBlock) k_count_s4(GraphView g, uint32_t *__restrict__ cnt,
-                                                          DevScalars *sc) {
-  constexpr uint32_t W = kCountBlock / 64;
-  constexpr uint32_t TC = R == 3 ? kC2Cap : 1;
-  __shared__ uint32_t s_v[W][kC2Cap];
-  __shared__ uint32_t s_eu[W][kC2Cap];
-  __shared__ uint32_t s_ev[W][kC2Cap];
-  __shared__ uint32_t s_t[W][TC];    // r = 3: id of triangle {u, v, w} per C2 entry
-  __shared__ uint32_t s_n[W][TC];    // r = 3: 4-cliques found so far through it
+                                                          DevScalars *sc, uint32_t cap) {
+  extern __shared__ uint32_t s_c2[];
   const uint32_t wv = threadIdx.x / 64;
   const uint32_t lane = lane_id();
-  uint32_t *cv = s_v[wv];
-  uint32_t *ceu = s_eu[wv];
-  uint32_t *cev = s_ev[wv];
-  uint32_t *ct = s_t[wv];
-  uint32_t *cn = s_n[wv];
+  uint32_t *cv = s_c2 + (uint64_t)count_s4_arrays<R>() * cap * wv;
+  uint32_t *ceu = cv + cap;
+  uint32_t *cev = ceu + cap;
+  uint32_t *ct = cev + cap;   // r = 3 only
+  uint32_t *cn = ct + cap;    // r = 3 only
   uint64_t local = 0;
-  const uint64_t nwaves = (uint64_t)gridDim.x * W;
-  for (uint64_t j = blockIdx.x * (uint64_t)W + wv; j < g.m; j += nwaves) {
+  const uint64_t nwaves = (uint64_t)gridDim.x * (kCountBlock / 64);
+  for (uint64_t j = blockIdx.x * (uint64_t)(kCountBlock / 64) + wv; j < g.m; j += nwaves) {
     const uint32_t u = segment_of(g.dgp, g.n, j);
     const uint32_t v = g.dgc[j];
     const uint32_t e_uv = g.dge[j];
@@ -125,19 +125,19 @@ __global__ void __launch_bounds__(kCountBlock) k_count_s4(GraphView g, uint32_t 
       if (hit) {
         uint64_t below = mask & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)));
         uint32_t slot = c + __popcll(below);
-        if (slot < kC2Cap) {
+        if (slot < cap) {
           cv[slot] = w;
           ceu[slot] = e_uw;
           cev[slot] = e_vw;
           if (R == 3) {
-            ct[slot % TC] = tri_lookup(g, u, v, w, e_uv, e_uw, e_vw);
-            cn[slot % TC] = 0;
+            ct[slot] = tri_lookup(g, u, v, w, e_uv, e_uw, e_vw);
+            cn[slot] = 0;
           }
         }
       }
       c += __popcll(mask);
     }
-    if (c > kC2Cap) {   // the host sizes launches so this cannot happen
+    if (c > cap) {   // the host sizes cap to the maximum out-degree, so this cannot happen
       if (lane == 0) atomicOr(&sc->status, ND_DERR_OVERFLOW);
       continue;
     }
@@ -177,8 +177,8 @@ __global__ void __launch_bounds__(kCountBlock) k_count_s4(GraphView g, uint32_t 
         // triangles {u,v,w} and {u,v,x} are counted per C2 entry (LDS),
         // {u,w,x} and {v,w,x} per 4-clique
         const uint32_t e_wx = g.dge[p];
-        atomicAdd(&cn[a % TC], 1u);
-        atomicAdd(&cn[b % TC], 1u);
+        atomicAdd(&cn[a], 1u);
+        atomicAdd(&cn[b], 1u);
         const uint32_t t2[2] = {tri_lookup(g, u, w, x, ceu[a], ceu[b], e_wx),
                                 tri_lookup(g, v, w, x, cev[a], cev[b], e_wx)};
 #pragma unroll
@@ -193,9 +193,9 @@ __global__ void __launch_bounds__(kCountBlock) k_count_s4(GraphView g, uint32_t 
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       for (uint32_t e = lane; e < c; e += 64) {
-        if (cn[e % TC] == 0) continue;
-        if (ct[e % TC] == ND_NONE) atomicOr(&sc->status, ND_DERR_BADGRAPH);
-        else atomicAdd(&cnt[ct[e % TC]], cn[e % TC]);
+        if (cn[e] == 0) continue;
+        if (ct[e] == ND_NONE) atomicOr(&sc->status, ND_DERR_BADGRAPH);
+        else atomicAdd(&cnt[ct[e]], cn[e]);
       }
     }
     __builtin_amdgcn_wave_barrier();
@@ -236,17 +236,33 @@ nd_status nd_stage_count(nd_ctx *c, const GraphView &g) {
     else
       hipLaunchKernelGGL(k_count_s3<2>, dim3(grid), dim3(kCountBlock), 0, c->stream, g, cnt, sc);
   } else if (s == 4 && g.m) {
-    // C2 fits the LDS buffer whenever the maximum out-degree does
-    if (c->info.max_outdeg > kC2Cap)
+    // C2 (common out-neighbours of an edge) has at most max-out-degree
+    // entries: the LDS arrays are sized to it, so that more workgroups fit
+    uint32_t maxd = 0;
+    if ((st = nd_hip(c, hipMemcpyAsync(&maxd, &sc->max_outdeg, 4, hipMemcpyDeviceToHost,
+                                       c->stream), "max out-degree")) != ND_OK ||
+        (st = nd_hip(c, hipStreamSynchronize(c->stream), "max out-degree")) != ND_OK)
+      return st;
+    c->info.max_outdeg = maxd;
+    if (maxd > kC2Cap)
       return nd_fail(c, ND_E_UNSUPPORTED,
                      "oriented out-degree exceeds the 4-clique listing buffer (1024)");
+    const uint32_t cap = std::max<uint32_t>(64, (maxd + 63) / 64 * 64);
     const uint32_t grid = nd_grid(g.m, kCountBlock / 64, 65536);
+    const void *kern = r == 1 ? (const void *)k_count_s4<1>
+                     : r == 2 ? (const void *)k_count_s4<2> : (const void *)k_count_s4<3>;
+    const uint32_t arrays = r == 1 ? count_s4_arrays<1>()
+                          : r == 2 ? count_s4_arrays<2>() : count_s4_arrays<3>();
+    const size_t lds = (size_t)(kCountBlock / 64) * arrays * cap * 4;
+    if ((st = nd_hip(c, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)lds), "count LDS size")) != ND_OK)
+      return st;
     if (r == 1)
-      hipLaunchKernelGGL(k_count_s4<1>, dim3(grid), dim3(kCountBlock), 0, c->stream, g, cnt, sc);
+      hipLaunchKernelGGL(k_count_s4<1>, dim3(grid), dim3(kCountBlock), lds, c->stream, g, cnt, sc, cap);
     else if (r == 2)
-      hipLaunchKernelGGL(k_count_s4<2>, dim3(grid), dim3(kCountBlock), 0, c->stream, g, cnt, sc);
+      hipLaunchKernelGGL(k_count_s4<2>, dim3(grid), dim3(kCountBlock), lds, c->stream, g, cnt, sc, cap);
     else
-      hipLaunchKernelGGL(k_count_s4<3>, dim3(grid), dim3(kCountBlock), 0, c->stream, g, cnt, sc);
+      hipLaunchKernelGGL(k_count_s4<3>, dim3(grid), dim3(kCountBlock), lds, c->stream, g, cnt, sc, cap);
   }
   st = nd_hip(c, hipGetLastError(), "count kernels");
   if (c->events_ok) (void)hipEventRecord(c->ev[8], c->stream);
