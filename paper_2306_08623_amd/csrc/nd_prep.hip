@@ -304,76 +304,111 @@ __global__ void k_dg_fill(uint32_t n, const uint64_t *__restrict__ rp,
 // edge -> triangle tables (r = 3)
 // ---------------------------------------------------------------------------
 
-// Calls f(w, slot_u, slot_v) for every common neighbour w of u and v in
-// ascending order. Probes the shorter row and binary-searches the longer.
-template <typename F>
-__device__ __forceinline__ void for_common(const uint64_t *rp, const uint32_t *col, uint32_t u,
-                                           uint32_t v, F f) {
-  uint64_t bu = rp[u], eu_ = rp[u + 1], bv = rp[v], ev_ = rp[v + 1];
-  if (eu_ - bu <= ev_ - bv) {
-    uint64_t lo = bv;
-    for (uint64_t i = bu; i < eu_; i++) {
-      uint32_t w = col[i];
-      lo = lower_bound_u32<uint64_t>(col, lo, ev_, w);
-      if (lo == ev_) break;
-      if (col[lo] == w) f(w, i, lo);
-    }
-  } else {
-    uint64_t lo = bu;
-    for (uint64_t i = bv; i < ev_; i++) {
-      uint32_t w = col[i];
-      lo = lower_bound_u32<uint64_t>(col, lo, eu_, w);
-      if (lo == eu_) break;
-      if (col[lo] == w) f(w, lo, i);
-    }
-  }
+// Triangle lists W(e) of every edge e = {u, v}, one wave per edge: the lanes
+// take the entries of the shorter of N(u), N(v), 64 at a time in ascending
+// order, and binary-search them in the longer list, so that an edge between
+// two hubs is spread over the wave instead of one thread. Common neighbours
+// come out in ascending order (ballot compaction in lane order).
+constexpr uint32_t kEtlBlock = 256;
+
+struct CommonScan {
+  uint64_t as, ae, bs, be;   // probed (shorter) list, searched list
+  bool u_short;              // the probed list is N(u)
+};
+
+__device__ __forceinline__ CommonScan common_scan(const uint64_t *rp, uint32_t u, uint32_t v) {
+  CommonScan c;
+  const uint64_t bu = rp[u], eu_ = rp[u + 1], bv = rp[v], ev_ = rp[v + 1];
+  c.u_short = eu_ - bu <= ev_ - bv;
+  c.as = c.u_short ? bu : bv;
+  c.ae = c.u_short ? eu_ : ev_;
+  c.bs = c.u_short ? bv : bu;
+  c.be = c.u_short ? ev_ : eu_;
+  return c;
 }
 
-__global__ void k_etl_count(uint64_t m, const uint64_t *__restrict__ rp,
-                            const uint32_t *__restrict__ col, const uint32_t *__restrict__ eu,
-                            const uint32_t *__restrict__ ev, uint32_t *__restrict__ sup,
-                            uint32_t *__restrict__ upc) {
-  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < m;
-       e += (uint64_t)gridDim.x * blockDim.x) {
-    uint32_t u = eu[e], v = ev[e];
+__global__ void __launch_bounds__(kEtlBlock) k_etl_count(uint64_t m, const uint64_t *__restrict__ rp,
+                                                         const uint32_t *__restrict__ col,
+                                                         const uint32_t *__restrict__ eu,
+                                                         const uint32_t *__restrict__ ev,
+                                                         uint32_t *__restrict__ sup,
+                                                         uint32_t *__restrict__ upc) {
+  const uint32_t lane = lane_id();
+  const uint64_t nwaves = (uint64_t)gridDim.x * (kEtlBlock / 64);
+  for (uint64_t e = blockIdx.x * (uint64_t)(kEtlBlock / 64) + threadIdx.x / 64; e < m;
+       e += nwaves) {
+    const uint32_t u = eu[e], v = ev[e];
+    const CommonScan c = common_scan(rp, u, v);
     uint32_t s = 0, up = 0;
-    for_common(rp, col, u, v, [&](uint32_t w, uint64_t, uint64_t) {
-      s++;
-      up += w > v;
-    });
-    sup[e] = s;
-    upc[e] = up;
+    for (uint64_t base = c.as; base < c.ae; base += 64) {
+      const uint64_t i = base + lane;
+      bool hit = false, above = false;
+      if (i < c.ae) {
+        const uint32_t w = col[i];
+        hit = find_u32<uint64_t>(col, c.bs, c.be, w) < c.be;
+        above = hit && w > v;
+      }
+      s += __popcll(ballot64(hit));
+      up += __popcll(ballot64(above));
+    }
+    if (lane == 0) {
+      sup[e] = s;
+      upc[e] = up;
+    }
   }
 }
 
-__global__ void k_etl_fill(uint64_t m, const uint64_t *__restrict__ rp,
-                           const uint32_t *__restrict__ col, const uint32_t *__restrict__ eid,
-                           const uint32_t *__restrict__ eu, const uint32_t *__restrict__ ev,
-                           const uint32_t *__restrict__ sup, const uint32_t *__restrict__ upc,
-                           const uint64_t *__restrict__ wp, const uint64_t *__restrict__ trib,
-                           uint32_t *__restrict__ wc, uint32_t *__restrict__ wt,
-                           uint32_t *__restrict__ te) {
-  for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < m;
-       e += (uint64_t)gridDim.x * blockDim.x) {
-    uint32_t u = eu[e], v = ev[e];
+__global__ void __launch_bounds__(kEtlBlock) k_etl_fill(uint64_t m, const uint64_t *__restrict__ rp,
+                                                        const uint32_t *__restrict__ col,
+                                                        const uint32_t *__restrict__ eid,
+                                                        const uint32_t *__restrict__ eu,
+                                                        const uint32_t *__restrict__ ev,
+                                                        const uint32_t *__restrict__ sup,
+                                                        const uint32_t *__restrict__ upc,
+                                                        const uint64_t *__restrict__ wp,
+                                                        const uint64_t *__restrict__ trib,
+                                                        uint32_t *__restrict__ wc,
+                                                        uint32_t *__restrict__ wt,
+                                                        uint32_t *__restrict__ te) {
+  const uint32_t lane = lane_id();
+  const uint64_t nwaves = (uint64_t)gridDim.x * (kEtlBlock / 64);
+  for (uint64_t e = blockIdx.x * (uint64_t)(kEtlBlock / 64) + threadIdx.x / 64; e < m;
+       e += nwaves) {
+    const uint32_t u = eu[e], v = ev[e];
+    const CommonScan c = common_scan(rp, u, v);
     uint64_t o = wp[e];
     const uint64_t first_up = wp[e] + (sup[e] - upc[e]);
     const uint64_t tb = trib[e];
-    for_common(rp, col, u, v, [&](uint32_t w, uint64_t su, uint64_t sv) {
-      wc[o] = w;
-      if (w > v) {
-        // triangle (u, v, w) owned by this edge
-        uint64_t t = tb + (o - first_up);
-        wt[o] = (uint32_t)t;
-        te[3 * t + 0] = (uint32_t)e;
-        te[3 * t + 1] = eid[su];
-        te[3 * t + 2] = eid[sv];
-      } else {
-        // owner is edge {u, w}: resolved once every list is filled
-        wt[o] = eid[su];
+    for (uint64_t base = c.as; base < c.ae; base += 64) {
+      const uint64_t i = base + lane;
+      bool hit = false;
+      uint32_t w = 0;
+      uint64_t p = 0;
+      if (i < c.ae) {
+        w = col[i];
+        p = find_u32<uint64_t>(col, c.bs, c.be, w);
+        hit = p < c.be;
       }
-      o++;
-    });
+      const uint64_t mask = ballot64(hit);
+      if (hit) {
+        const uint64_t below = mask & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)));
+        const uint64_t slot = o + __popcll(below);
+        const uint64_t su = c.u_short ? i : p, sv = c.u_short ? p : i;   // w's slots in N(u), N(v)
+        wc[slot] = w;
+        if (w > v) {
+          // triangle (u, v, w) owned by this edge
+          const uint64_t t = tb + (slot - first_up);
+          wt[slot] = (uint32_t)t;
+          te[3 * t + 0] = (uint32_t)e;
+          te[3 * t + 1] = eid[su];
+          te[3 * t + 2] = eid[sv];
+        } else {
+          // owner is edge {u, w}: resolved once every list is filled
+          wt[slot] = eid[su];
+        }
+      }
+      o += __popcll(mask);
+    }
   }
 }
 
@@ -715,8 +750,8 @@ nd_status nd_stage_prep(nd_ctx *c, GraphView *gv) {
     if (!wp) return st;
     uint64_t *trib = (uint64_t *)nd_buf(c, B_TRIB, (m + 1) * 8, &st);
     if (!trib) return st;
-    hipLaunchKernelGGL(k_etl_count, dim3(nd_grid(m, 256, 16384)), dim3(256), 0, c->stream, m, rp,
-                       col, eu, ev, sup, upc);
+    hipLaunchKernelGGL(k_etl_count, dim3(nd_grid(m, kEtlBlock / 64, 65536)), dim3(kEtlBlock), 0,
+                       c->stream, m, rp, col, eu, ev, sup, upc);
     uint64_t nw = 0, ntri = 0;
     st = nd_exclusive_scan_u32_to_u64(c, sup, wp, m, &nw);
     if (st != ND_OK) return st;
@@ -732,8 +767,8 @@ nd_status nd_stage_prep(nd_ctx *c, GraphView *gv) {
     uint32_t *te = (uint32_t *)nd_buf(c, B_TE, std::max<uint64_t>(3 * ntri, 1) * 4, &st);
     if (!te) return st;
     if (nw) {
-      hipLaunchKernelGGL(k_etl_fill, dim3(nd_grid(m, 256, 16384)), dim3(256), 0, c->stream, m, rp,
-                         col, eid, eu, ev, sup, upc, wp, trib, wc, wt, te);
+      hipLaunchKernelGGL(k_etl_fill, dim3(nd_grid(m, kEtlBlock / 64, 65536)), dim3(kEtlBlock), 0,
+                         c->stream, m, rp, col, eid, eu, ev, sup, upc, wp, trib, wc, wt, te);
       hipLaunchKernelGGL(k_etl_resolve, dim3(nd_grid(nw, 256, 65536)), dim3(256), 0, c->stream, m,
                          nw, ev, wp, wc, wt, &sc->status);
     }
