@@ -31,13 +31,39 @@ __device__ __forceinline__ uint32_t tfind(const uint32_t *uf, uint32_t x) {
   }
 }
 
+// Groups the active lanes of a wave by key: returns the group's size in its
+// lowest lane (`first` set there), 0 elsewhere. A few large components or
+// nodes take most updates; one atomic per group and wave instead of one per
+// lane takes the contention off them.
+__device__ __forceinline__ uint32_t wave_group(uint32_t key, bool active, bool &first) {
+  const uint32_t lane = lane_id();
+  uint64_t pending = ballot64(active);
+  uint32_t count = 0;
+  first = false;
+  while (pending) {
+    const uint32_t leader = __ffsll((unsigned long long)pending) - 1;
+    const uint32_t k = __shfl(key, leader, 64);
+    const uint64_t same = ballot64(active && key == k);
+    if (lane == leader) {
+      first = true;
+      count = __popcll(same);
+    }
+    pending &= ~same;
+  }
+  return count;
+}
+
 __global__ void k_roots(uint64_t n, const uint32_t *__restrict__ uf, uint32_t *__restrict__ root,
                         uint32_t *__restrict__ sz) {
-  for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n;
-       x += (uint64_t)gridDim.x * blockDim.x) {
-    uint32_t rt = tfind(uf, (uint32_t)x);
-    root[x] = rt;
-    atomicAdd(&sz[rt], 1u);
+  for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x; base < n;
+       base += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t x = base + threadIdx.x;
+    const bool active = x < n;
+    const uint32_t rt = active ? tfind(uf, (uint32_t)x) : 0;
+    if (active) root[x] = rt;
+    bool first;
+    const uint32_t cnt = wave_group(rt, active, first);
+    if (first) atomicAdd(&sz[rt], cnt);
   }
 }
 
@@ -72,9 +98,15 @@ __global__ void k_minleaf(uint64_t n, const uint32_t *__restrict__ root,
                           const uint32_t *__restrict__ sz, const uint32_t *__restrict__ nkid,
                           const uint32_t *__restrict__ npar, uint32_t *__restrict__ ml,
                           uint32_t *status) {
-  for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n;
-       x += (uint64_t)gridDim.x * blockDim.x) {
-    uint32_t node = leaf_parent(root, sz, nkid, npar, (uint32_t)x);
+  for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x; base < n;
+       base += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t x = base + threadIdx.x;
+    uint32_t node = x < n ? leaf_parent(root, sz, nkid, npar, (uint32_t)x) : ND_NONE;
+    // of the lanes that start at one node only the lowest (the smallest leaf
+    // id, lanes take consecutive leaves) can lower a minimum on its path
+    bool first;
+    (void)wave_group(node, node != ND_NONE, first);
+    if (!first) continue;
     // levels strictly decrease along npar, so the walk is finite; the cap
     // only guards against a corrupted table
     for (uint32_t hop = 0; node != ND_NONE; hop++) {
