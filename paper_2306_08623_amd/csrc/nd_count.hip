@@ -83,10 +83,11 @@ __global__ void __launch_bounds__(kCountBlock) k_count_s3(GraphView g, uint32_t 
 }
 
 // LDS arrays of `cap` entries per wave: C2 vertices, their edge ids to u and
-// to v, and for r = 3 the triangle {u, v, w} of each entry and the 4-cliques
-// found so far through it
+// to v, and for r = 3 the 4-cliques found so far through the triangle
+// {u, v, w} of each entry (its id is looked up when that count is flushed,
+// only for entries that have 4-cliques)
 template <int R>
-constexpr uint32_t count_s4_arrays() { return R == 3 ? 5 : 3; }
+constexpr uint32_t count_s4_arrays() { return R == 3 ? 4 : 3; }
 
 template <int R>
 __global__ void __launch_bounds__(kCountBlock) k_count_s4(GraphView g, uint32_t *__restrict__ cnt,
@@ -97,8 +98,7 @@ __global__ void __launch_bounds__(kCountBlock) k_count_s4(GraphView g, uint32_t 
   uint32_t *cv = s_c2 + (uint64_t)count_s4_arrays<R>() * cap * wv;
   uint32_t *ceu = cv + cap;
   uint32_t *cev = ceu + cap;
-  uint32_t *ct = cev + cap;   // r = 3 only
-  uint32_t *cn = ct + cap;    // r = 3 only
+  uint32_t *cn = cev + cap;   // r = 3 only
   uint64_t local = 0;
   const uint64_t nwaves = (uint64_t)gridDim.x * (kCountBlock / 64);
   for (uint64_t j = blockIdx.x * (uint64_t)(kCountBlock / 64) + wv; j < g.m; j += nwaves) {
@@ -129,10 +129,7 @@ __global__ void __launch_bounds__(kCountBlock) k_count_s4(GraphView g, uint32_t 
           cv[slot] = w;
           ceu[slot] = e_uw;
           cev[slot] = e_vw;
-          if (R == 3) {
-            ct[slot] = tri_lookup(g, u, v, w, e_uv, e_uw, e_vw);
-            cn[slot] = 0;
-          }
+          if (R == 3) cn[slot] = 0;
         }
       }
       c += __popcll(mask);
@@ -194,8 +191,9 @@ __global__ void __launch_bounds__(kCountBlock) k_count_s4(GraphView g, uint32_t 
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       for (uint32_t e = lane; e < c; e += 64) {
         if (cn[e] == 0) continue;
-        if (ct[e] == ND_NONE) atomicOr(&sc->status, ND_DERR_BADGRAPH);
-        else atomicAdd(&cnt[ct[e]], cn[e]);
+        const uint32_t t = tri_lookup(g, u, v, cv[e], e_uv, ceu[e], cev[e]);
+        if (t == ND_NONE) atomicOr(&sc->status, ND_DERR_BADGRAPH);
+        else atomicAdd(&cnt[t], cn[e]);
       }
     }
     __builtin_amdgcn_wave_barrier();
