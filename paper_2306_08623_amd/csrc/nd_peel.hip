@@ -488,11 +488,11 @@ struct Shape<3, 4> {
     const uint64_t p0 = g.wp[e0] + i;
     const uint32_t x = g.wc[p0];
     const uint64_t b1 = g.wp[e1], f1 = g.wp[e1 + 1];
-    const uint64_t p1 = find_u32<uint64_t>(g.wc, b1, f1, x);
-    if (p1 == f1) return false;
     const uint64_t b2 = g.wp[e2], f2 = g.wp[e2 + 1];
-    const uint64_t p2 = find_u32<uint64_t>(g.wc, b2, f2, x);
-    if (p2 == f2) return false;
+    if (b1 == f1 || b2 == f2) return false;   // never: each holds R's third vertex
+    uint64_t p1, p2;
+    find2_u32<uint64_t>(g.wc, b1, f1, b2, f2, x, p1, p2);
+    if (p1 == f1 || p2 == f2) return false;
     o[0] = g.wt[p0];
     o[1] = g.wt[p1];
     o[2] = g.wt[p2];
