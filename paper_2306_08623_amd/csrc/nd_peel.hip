@@ -84,13 +84,48 @@ __device__ __forceinline__ uint32_t uf_find(uint32_t *uf, uint32_t x) {
   }
 }
 
+// The roots of x and y, the two walks in lockstep (their dependent loads
+// overlap), each with the path halving of uf_find.
+__device__ __forceinline__ void uf_find2(uint32_t *uf, uint32_t &x, uint32_t &y) {
+  bool dx = false, dy = false;
+  for (;;) {
+    uint32_t px = x, py = y;
+    if (!dx) px = ld_acq32(&uf[x]);
+    if (!dy) py = ld_acq32(&uf[y]);
+    dx |= px == x;
+    dy |= py == y;
+    if (dx && dy) return;
+    uint32_t gx = px, gy = py;
+    if (!dx) gx = ld_acq32(&uf[px]);
+    if (!dy) gy = ld_acq32(&uf[py]);
+    if (!dx) {
+      if (gx == px) {
+        x = px;
+        dx = true;
+      } else {
+        cas32(&uf[x], px, gx);
+        x = gx;
+      }
+    }
+    if (!dy) {
+      if (gy == py) {
+        y = py;
+        dy = true;
+      } else {
+        cas32(&uf[y], py, gy);
+        y = gy;
+      }
+    }
+    if (dx && dy) return;
+  }
+}
+
 // Joins the sets of a and b; the smaller root id survives. Returns the root
 // whose parent pointer this call changed (the loser), or ND_NONE when a and b
 // were already in one set.
 __device__ __forceinline__ uint32_t uf_unite(uint32_t *uf, uint32_t a, uint32_t b) {
   for (;;) {
-    a = uf_find(uf, a);
-    b = uf_find(uf, b);
+    uf_find2(uf, a, b);
     if (a == b) return ND_NONE;
     if (a > b) { uint32_t t = a; a = b; b = t; }
     if (cas32(&uf[b], b, a)) return b;
@@ -135,8 +170,7 @@ __device__ __forceinline__ uint32_t link_step(LinkCtx &c, uint32_t R, uint32_t Q
   if (R == ND_NONE || Q == ND_NONE) return 0;
   c.links++;
   if (c.nd[Q] < c.nd[R]) { uint32_t t = R; R = Q; Q = t; }
-  R = uf_find(c.uf, R);
-  Q = uf_find(c.uf, Q);
+  uf_find2(c.uf, R, Q);
   const uint32_t ndR = c.nd[R];
   if (ndR == c.nd[Q]) {
     if (R == Q) return 0;
@@ -631,6 +665,21 @@ __device__ __forceinline__ uint32_t key_root(const uint32_t *uf, uint32_t x) {
   }
 }
 
+// key_root of x and of y, the two walks in lockstep
+__device__ __forceinline__ void key_root2(const uint32_t *uf, uint32_t &x, uint32_t &y) {
+  bool dx = false, dy = false;
+  for (;;) {
+    uint32_t px = x, py = y;
+    if (!dx) px = uf[x];
+    if (!dy) py = uf[y];
+    dx |= px == x;
+    dy |= py == y;
+    x = px;
+    y = py;
+    if (dx && dy) return;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // the persistent kernel
 // ---------------------------------------------------------------------------
@@ -920,8 +969,13 @@ __global__ void __launch_bounds__(kPeelBlock, 5) k_peel(PeelArgs a) {
 #pragma unroll
           for (int j = 0; j < NO; j++) {
             if (kLink && (rr[j] == kPeeledBefore || (rr[j] == kPeeledNow && R < others[j]))) {
-              if (qroot == ND_NONE) qroot = key_root(a.uf, R);
-              const uint32_t x = key_root(a.uf, others[j]);
+              uint32_t x = others[j];
+              if (qroot == ND_NONE) {
+                qroot = R;
+                key_root2(a.uf, qroot, x);
+              } else {
+                x = key_root(a.uf, x);
+              }
               if (x == qroot || lcache_hit(s_lcache, x, qroot)) continue;
               const uint64_t key = ((uint64_t)x << 32) | qroot;
               uint64_t *gslot = &a.gcache[gcache_slot(x, qroot, a.gcache_mask)];
