@@ -169,10 +169,18 @@ __device__ __forceinline__ uint32_t link_step(LinkCtx &c, uint32_t R, uint32_t Q
   };
   if (R == ND_NONE || Q == ND_NONE) return 0;
   c.links++;
-  if (c.nd[Q] < c.nd[R]) { uint32_t t = R; R = Q; Q = t; }
+  // roots first, then the order by core number: a union-find set only ever
+  // joins r-cliques of one core number, so a root's is its members'
   uf_find2(c.uf, R, Q);
-  const uint32_t ndR = c.nd[R];
-  if (ndR == c.nd[Q]) {
+  uint32_t ndR = c.nd[R], ndQ = c.nd[Q];
+  if (ndQ < ndR) {
+    const uint32_t t = R, tn = ndR;
+    R = Q;
+    Q = t;
+    ndR = ndQ;
+    ndQ = tn;
+  }
+  if (ndR == ndQ) {
     if (R == Q) return 0;
     const uint32_t loser = uf_unite(c.uf, R, Q);   // hand-over as in link_efficient
     if (loser != ND_NONE) {
