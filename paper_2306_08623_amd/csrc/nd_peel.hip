@@ -579,21 +579,25 @@ struct Shape<2, 4> {
     const uint32_t x1 = xs[0], x2 = xs[1];
     const uint32_t which = sl >> 30, off = sl & 0x3FFFFFFFu;
     uint64_t pR, p1;
+    // the two list searches of either case advance in lockstep (all lists
+    // searched hold t's third vertex, so none is empty)
     if (which == 0) {
       pR = b + off + j;
       const uint32_t x = g.wc[pR];
-      p1 = find_u32<uint64_t>(g.wc, g.wp[x1], g.wp[x1 + 1], x);
-      if (p1 == g.wp[x1 + 1]) return false;
-      const uint64_t p2 = find_u32<uint64_t>(g.wc, g.wp[x2], g.wp[x2 + 1], x);
-      if (p2 == g.wp[x2 + 1]) return false;
+      const uint64_t b1 = g.wp[x1], f1 = g.wp[x1 + 1], b2 = g.wp[x2], f2 = g.wp[x2 + 1];
+      if (b1 == f1 || b2 == f2) return false;
+      uint64_t p2;
+      find2_u32<uint64_t>(g.wc, b1, f1, b2, f2, x, p1, p2);
+      if (p1 == f1 || p2 == f2) return false;
     } else {
       const uint32_t ep = which == 1 ? x1 : x2, eo = which == 1 ? x2 : x1;
       const uint64_t pp = g.wp[ep] + off + j;
       const uint32_t x = g.wc[pp];
-      const uint64_t po = find_u32<uint64_t>(g.wc, g.wp[eo], g.wp[eo + 1], x);
-      if (po == g.wp[eo + 1]) return false;
-      pR = find_u32<uint64_t>(g.wc, b, f, x);
-      if (pR == f) return false;
+      const uint64_t bo = g.wp[eo], fo = g.wp[eo + 1];
+      if (bo == fo || b == f) return false;
+      uint64_t po;
+      find2_u32<uint64_t>(g.wc, bo, fo, b, f, x, po, pR);
+      if (po == fo || pR == f) return false;
       p1 = which == 1 ? pp : po;
     }
     // triangle {u,v,x}: its edges other than R are {u,x}, {v,x}
@@ -912,6 +916,7 @@ __global__ void __launch_bounds__(kPeelBlock, 5) k_peel(PeelArgs a) {
     const uint64_t P = s_boff[nb];
     uint64_t *wq = s_lq[kLink ? wv : 0];
     uint32_t qn = 0;   // pending link steps of this wave (uniform)
+    uint32_t seg_hint = 0;   // this lane's segment in its previous pass (units only grow)
     for (uint64_t base = blockIdx.x * (uint64_t)kPeelBlock + wv * 64ull; base < P;
          base += nthreads) {
       const uint64_t p = base + lane;
@@ -924,13 +929,24 @@ __global__ void __launch_bounds__(kPeelBlock, 5) k_peel(PeelArgs a) {
         lpair[j] = ~0ull;
       }
       if (p < P) {
-        // block segment holding unit p, then the frontier slot inside it
-        uint32_t lo = 0, hi = nb;   // s_boff[lo] <= p < s_boff[hi]
+        // block segment holding unit p (s_boff[lo] <= p < s_boff[hi]): a
+        // binary search in the first pass, a gallop from the previous
+        // segment after it; then the frontier slot inside the segment
+        uint32_t lo = seg_hint, hi = nb;
+        if (lo != 0) {
+          uint32_t step = 1;
+          while (lo + step < nb && s_boff[lo + step] <= p) {
+            lo += step;
+            step <<= 1;
+          }
+          hi = lo + step < nb ? lo + step : nb;
+        }
         while (hi - lo > 1) {
           uint32_t mid = (lo + hi) >> 1;
           if (s_boff[mid] <= p) lo = mid;
           else hi = mid;
         }
+        seg_hint = lo;
         const uint64_t qoff = p - s_boff[lo];
         const uint64_t b0 = min64((uint64_t)lo * seg, f);
         const uint64_t b1 = min64(b0 + seg, f);
@@ -963,14 +979,17 @@ __global__ void __launch_bounds__(kPeelBlock, 5) k_peel(PeelArgs a) {
             dead |= rr[j] == kPeeledBefore;
             lead &= !(rr[j] == kPeeledNow && others[j] < R);
           }
-          if (!dead && lead) {
+          // decrements first; their old values are only compared after the
+          // link checks below, so the atomics stay in flight meanwhile
+          uint32_t oldc[NO];
+          bool dec[NO];
 #pragma unroll
-            for (int j = 0; j < NO; j++) {
-              if (rr[j] == kAlive) {
-                uint32_t old = atomicSub(&a.cnt[others[j]], 1u);
-                decs++;
-                push[j] = (old == k + 1);
-              }
+          for (int j = 0; j < NO; j++) {
+            dec[j] = !dead && lead && rr[j] == kAlive;
+            oldc[j] = 0;
+            if (dec[j]) {
+              oldc[j] = atomicSub(&a.cnt[others[j]], 1u);
+              decs++;
             }
           }
           uint32_t qroot = ND_NONE;   // cache key of R's set, formed on first use
@@ -997,6 +1016,8 @@ __global__ void __launch_bounds__(kPeelBlock, 5) k_peel(PeelArgs a) {
               atomicExch((unsigned long long *)gslot, (unsigned long long)key);
             }
           }
+#pragma unroll
+          for (int j = 0; j < NO; j++) push[j] = dec[j] && oldc[j] == k + 1;
         }
       }
 #pragma unroll
