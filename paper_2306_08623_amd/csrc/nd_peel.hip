@@ -950,12 +950,10 @@ __global__ void __launch_bounds__(kPeelBlock, 5) k_peel(PeelArgs a) {
         const uint64_t qoff = p - s_boff[lo];
         const uint64_t b0 = min64((uint64_t)lo * seg, f);
         const uint64_t b1 = min64(b0 + seg, f);
-        // first slot with wscan > qoff: lane 0 binary-searches its segment;
-        // the other lanes of the wave (consecutive units, mostly of the same
-        // r-clique) gallop forward from lane 0's slot when they share its
-        // segment
+        // first slot with wscan > qoff: every lane searches for itself (the
+        // lanes take consecutive units, so their loads mostly share lines)
         uint64_t x0 = b0;
-        if (lane == 0) {
+        {
           uint64_t x1 = b1;
           while (x0 < x1) {
             uint64_t mid = (x0 + x1) >> 1;
@@ -963,9 +961,6 @@ __global__ void __launch_bounds__(kPeelBlock, 5) k_peel(PeelArgs a) {
             else x1 = mid;
           }
         }
-        const uint32_t lo_l0 = __shfl(lo, 0, 64);
-        const uint64_t x_l0 = __shfl(x0, 0, 64);
-        if (lane != 0) x0 = gallop_u64(a.wscan, lo == lo_l0 ? x_l0 : b0, b1, qoff);
         const uint32_t R = F[x0];
         const uint64_t before = (x0 > b0) ? a.wscan[x0 - 1] : 0;
         const uint32_t idx = (uint32_t)(qoff - before);
