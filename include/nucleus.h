@@ -149,9 +149,13 @@ nd_status nd_set_rs(nd_ctx *ctx, uint32_t r, uint32_t s);
  * canonical numbering. Two kernels of the pipeline (orientation, peel) are
  * persistent grids that synchronise all their workgroups: while they run,
  * no other kernel should occupy the GPU (they stop with ND_E_WATCHDOG after
- * 20 s without progress instead of hanging). Blocks once on a small readback of the r-clique count
- * (needed to size the per-r-clique arrays) and at the end; results stay on
- * the device until read with nd_get_*. */
+ * 20 s without progress instead of hanging). Blocks on small readbacks of
+ * the r-clique count (needed to size the per-r-clique arrays) and, for s = 4,
+ * of the largest out-degree of the orientation (it sizes the counting
+ * kernel's on-chip buffers), and at the end; results stay on the device
+ * until read with nd_get_*. For s = 4 an orientation whose largest
+ * out-degree exceeds 1024 (a graph of degeneracy above 1024) returns
+ * ND_E_UNSUPPORTED before counting. */
 nd_status nd_decompose(nd_ctx *ctx);
 
 /* Wait for the context's stream and report device-side errors. */
