@@ -319,7 +319,7 @@ def main() -> int:
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on exactly one GPU: the decomposition of one graph is not "
-              "sharded across GPUs in this build (see DESIGN.md, 'Sharding').", file=sys.stderr)
+              "sharded across GPUs.", file=sys.stderr)
         return 2
     r, s = (int(x) for x in args.rs.split(","))
 
