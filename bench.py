@@ -35,9 +35,12 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic bytes of the dominant kernels ("Roofline"):
-#   peel+link kernel: bytes per (r-clique, s-clique) visit and per peeled
-#   r-clique; counting kernel: bytes per listed s-clique.
+# Algorithmic bytes of the dominant kernels: peel+link kernel, bytes per
+# (r-clique, s-clique) visit and per peeled r-clique; counting kernel, bytes
+# per listed s-clique. For (3,4) a visit reads its probe entry (8 B), the two
+# matched list entries (16 B) and three peel states (12 B), and updates three
+# counts (24 B); a 4-clique costs four triangle-id lookups and four count
+# updates (8 B each).
 PEEL_BYTES_PER_VISIT = {(1, 2): 16, (2, 3): 40, (3, 4): 60, (2, 4): 96}
 PEEL_BYTES_PER_RCLIQUE = {(1, 2): 20, (2, 3): 24, (3, 4): 28, (2, 4): 28}
 COUNT_BYTES_PER_SCLIQUE = {(1, 2): 0, (2, 3): 36, (3, 4): 64, (2, 4): 72}

@@ -49,7 +49,7 @@ typedef enum nd_status {
   ND_OK = 0,
   ND_E_INVALID_ARG = 1,   /* NULL pointer, r/s out of range, bad sizes       */
   ND_E_BAD_GRAPH = 2,     /* CSR not symmetric / sorted / simple             */
-  ND_E_UNSUPPORTED = 3,   /* (r,s) pair or size this build does not handle   */
+  ND_E_UNSUPPORTED = 3,   /* (r,s) pair or size the library does not handle  */
   ND_E_OOM = 4,           /* device allocation failed or memory limit hit    */
   ND_E_OVERFLOW = 5,      /* a 32-bit count or id would overflow             */
   ND_E_DEVICE = 6,        /* a HIP runtime call failed                       */
