@@ -282,3 +282,36 @@ def test_rejects_bad_graphs():
     assert oracle.validate(CSR(2, rp, col)) == oracle.NDO_E_BAD_GRAPH
     with pytest.raises(oracle.OracleError):
         oracle.decompose(I.complete(4), 2, 2)
+
+
+def _csr_rows(rows):
+    from paper_2306_08623_amd.inputs import CSR
+    rp = np.zeros(len(rows) + 1, dtype=np.uint64)
+    for i, row in enumerate(rows):
+        rp[i + 1] = rp[i] + len(row)
+    col = np.array([x for row in rows for x in row], dtype=np.uint32)
+    return CSR(len(rows), rp, col)
+
+
+def test_rejects_duplicate_and_unsorted_rows():
+    """A simple graph (Section 3) has no parallel edges: a row listing a
+    neighbour twice, or out of ascending order, is not a valid CSR of one.
+    Each case below is symmetric and loop-free, so only the row-order check
+    can reject it; the valid triangle next to them must pass."""
+    tri = [[1, 2], [0, 2], [0, 1]]
+    assert oracle.validate(_csr_rows(tri)) == oracle.NDO_OK
+    dup = [[1, 1, 2], [0, 0, 2], [0, 1]]          # edge {0,1} listed twice in both rows
+    assert oracle.validate(_csr_rows(dup)) == oracle.NDO_E_BAD_GRAPH
+    dup_one_side = [[1, 2, 2], [0, 2], [0, 0, 1]]  # {0,2} twice in rows 0 and 2
+    assert oracle.validate(_csr_rows(dup_one_side)) == oracle.NDO_E_BAD_GRAPH
+    unsorted = [[2, 1], [0, 2], [0, 1]]            # row 0 descending
+    assert oracle.validate(_csr_rows(unsorted)) == oracle.NDO_E_BAD_GRAPH
+    unsorted_last = [[1, 2], [0, 2], [1, 0]]       # the last row descending
+    assert oracle.validate(_csr_rows(unsorted_last)) == oracle.NDO_E_BAD_GRAPH
+    out_of_range = [[1, 3], [0], [], []]           # neighbour id 3 of row 0 has no twin 0
+    assert oracle.validate(_csr_rows(out_of_range)) == oracle.NDO_E_BAD_GRAPH
+    from paper_2306_08623_amd.inputs import CSR
+    big = CSR(2, np.array([0, 1, 2], dtype=np.uint64), np.array([5, 0], dtype=np.uint32))
+    assert oracle.validate(big) == oracle.NDO_E_BAD_GRAPH   # id >= n
+    with pytest.raises(oracle.OracleError):
+        oracle.decompose(_csr_rows(dup), 1, 2)
