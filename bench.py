@@ -1,16 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark: exact (3,4) nucleus decomposition + hierarchy on one MI355X.
 
-Workload: R-MAT scale 18 (262,144 vertices), edge factor 16,
-(a,b,c,d) = (0.57, 0.19, 0.19, 0.05), seed 2, symmetrised and deduplicated;
-(r,s) = (3,4). A step is one full decomposition from the CSR already resident
-in HBM: orientation, triangle tables, 4-clique counting, the peel rounds with
-hierarchy linking, and the canonical tree.
+Workload (the largest (3,4) configuration): a Chung-Lu power-law graph with
+n = 4,000,000, degree exponent 2.1, ~40M sampled edges, maximum expected
+degree 20,000, plus 1,000 disjoint communities of 20-200 vertices at edge
+density 0.6, seed 3; (r,s) = (3,4). A step is one full decomposition from
+the CSR already resident in HBM: orientation, triangle tables, 4-clique
+counting, the peel rounds with hierarchy linking, and the canonical tree.
+R-MAT scale 18 (edge factor 16, (a,b,c,d) = (.57,.19,.19,.05), seed 2) is
+measured the same way as a secondary object of the line.
 
 Metric: s-cliques traversed per second, where a decomposition traverses
 n_s + C(s,r) * n_s s-cliques (each s-clique once while counting, and once per
 member r-clique while peeling). The same numerator is used for the CPU
-oracle baseline, which runs on a smaller R-MAT of the same generator.
+oracle baseline, which runs on a smaller graph of the same generator.
 
 The same line carries a "batch" object: the 4,096-graph mixed batch
 (n log-uniform in [64, 65536], Erdos-Renyi or Chung-Lu with planted cliques,
@@ -37,57 +40,109 @@ HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes of the dominant kernels: peel+link kernel, bytes per
 # (r-clique, s-clique) visit and per peeled r-clique; counting kernel, bytes
-# per listed s-clique. For (3,4) a visit reads its probe entry (8 B), the two
-# matched list entries (16 B) and three peel states (12 B), and updates three
-# counts (24 B); a 4-clique costs four triangle-id lookups and four count
-# updates (8 B each).
-PEEL_BYTES_PER_VISIT = {(1, 2): 16, (2, 3): 40, (3, 4): 60, (2, 4): 96}
-PEEL_BYTES_PER_RCLIQUE = {(1, 2): 20, (2, 3): 24, (3, 4): 28, (2, 4): 28}
-COUNT_BYTES_PER_SCLIQUE = {(1, 2): 0, (2, 3): 36, (3, 4): 64, (2, 4): 72}
+# per listed s-clique. A visit resolves the ids of the s-clique's other
+# r-cliques (4 B per edge id from a CSR slot, 8 B per triangle id: list
+# entry + its triangle) and touches each one's state (a 4 B peel state and
+# an 8 B count read-modify-write): (3,4) 3 x (8 + 12) = 60 B, (2,3)
+# 2 x (4 + 12) = 32 B, (2,4) 5 x (4 + 12) = 80 B, (1,2) 16 B, (1,3) 2 x 16,
+# (1,4) 3 x 16 (a vertex id instead of an r-clique id). A peeled r-clique
+# adds its frontier slot (write + read), core number and peel round, and its
+# probe range offsets. A counted 4-clique costs four triangle-id lookups and
+# four count updates (8 B each).
+PEEL_BYTES_PER_VISIT = {(1, 2): 16, (2, 3): 32, (3, 4): 60, (2, 4): 80, (1, 3): 32, (1, 4): 48}
+PEEL_BYTES_PER_RCLIQUE = {(1, 2): 20, (2, 3): 24, (3, 4): 28, (2, 4): 28, (1, 3): 20, (1, 4): 20}
+COUNT_BYTES_PER_SCLIQUE = {(1, 2): 0, (2, 3): 36, (3, 4): 64, (2, 4): 72, (1, 3): 36, (1, 4): 48}
+
+DESCS = {
+    "chunglu4m": "Chung-Lu n=4,000,000, exponent 2.1, ~40M edges, max expected degree 20,000, "
+                 "+ 1,000 communities of size 20..200 at density 0.6, seed 3",
+    "rmat18": "R-MAT scale 18, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), seed 2",
+    "er2k": "G(2000, 0.01) + 20 planted cliques of size 5..30, seed 1",
+}
 
 
-PROFILE = os.path.join(ROOT, "profiles", "k_peel_rmat18_34.txt")
+def profile_path(kernel: str, workload_name: str, r: int, s: int) -> str:
+    return os.path.join(ROOT, "profiles", f"{kernel}_{workload_name}_{r}{s}.txt")
 
 
 def measured_traffic(kernel: str, workload_name: str, r: int, s: int):
-    """HBM bytes per launch from the committed rocprofv3 --pmc summary
-    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
-    if this workload was not profiled or the peel kernel's source changed
-    since the counters were taken."""
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary of
+    this kernel on this workload (FETCH_SIZE + WRITE_SIZE, scaled by the
+    copy-kernel calibration), or None if it was not profiled or the kernel's
+    source changed since the counters were taken."""
     import hashlib
-    if workload_name != "rmat18" or (r, s) != (3, 4) or not os.path.exists(PROFILE):
+    path = profile_path("k_peel", workload_name, r, s)
+    if not os.path.exists(path):
         return None
-    text = open(PROFILE).read()
+    text = open(path).read()
     src = os.path.join(ROOT, "paper_2306_08623_amd", "csrc")
-    h = hashlib.sha256(open(os.path.join(src, "nd_peel.hip"), "rb").read() +
-                       open(os.path.join(src, "nd_internal.h"), "rb").read()).hexdigest()
-    if f"when measured: {h}" not in text:
+    files = {"k_peel": ("nd_peel.hip", "nd_internal.h"),
+             "k_count_s4": ("nd_count.hip", "nd_internal.h")}.get(kernel)
+    if files is None:
         return None
-    key = {"k_peel": "k_peel<3,4>", "k_count_s4": "k_count_s4<3>"}.get(kernel)
+    h = hashlib.sha256(b"".join(open(os.path.join(src, f), "rb").read()
+                                for f in files)).hexdigest()
+    key = f"traffic_bytes_per_launch {kernel}<{r},{s}> {workload_name} source {h}:"
     for line in text.splitlines():
-        if key and line.startswith(f"traffic_bytes_per_launch {key} rmat18:"):
+        if line.startswith(key):
             return int(line.split(":")[1])
     return None
 
 
 def workload(name: str):
     from paper_2306_08623_amd import inputs as I
+    if name == "chunglu4m":
+        return I.workload_chung_lu_4m(), DESCS[name]
     if name == "rmat18":
-        return I.workload_rmat18(), "R-MAT scale 18, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), seed 2"
+        return I.workload_rmat18(), DESCS[name]
     if name == "er2k":
-        return I.workload_er2k(), "G(2000, 0.01) + 20 planted cliques of size 5..30, seed 1"
+        return I.workload_er2k(), DESCS[name]
     if name.startswith("rmat"):
         sc = int(name[4:])
         return I.rmat(sc, 16, 2), f"R-MAT scale {sc}, edge factor 16, seed 2"
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(r: int, s: int, scale: int) -> dict:
-    """The oracle, single-threaded, on R-MAT at a smaller scale (same
-    generator parameters and seed): traversals per second."""
-    import oracle
+def cpu_sample(name: str, scale: int):
+    """A smaller graph of the benched workload's generator, for the oracle."""
     from paper_2306_08623_amd import inputs as I
-    g = I.rmat(scale, 16, 2)
+    if name == "chunglu4m":
+        # same exponent, mean degree and community recipe; n, the maximum
+        # expected degree and the number of communities shrink by 2^scale
+        n = 4_000_000 >> scale
+        wmax = 20_000.0 / (1 << scale)
+        comms = max(1, 1000 >> scale)
+        g = I.chung_lu(n, 2.1, 20.0, wmax, 3, target_edges=10 * n, n_communities=comms,
+                       comm_lo=20, comm_hi=200, comm_density=0.6)
+        return g, (f"Chung-Lu n={n}, exponent 2.1, mean degree 20, max expected degree {wmax:.0f}, "
+                   f"+ {comms} communities of size 20..200 at density 0.6, seed 3 (the "
+                   f"benched generator with n, max degree and communities / {1 << scale})")
+    sc = scale if not name.startswith("rmat") else int(name[4:]) - scale
+    return I.rmat(sc, 16, 2), f"R-MAT scale {sc}, edge factor 16, seed 2 (same generator)"
+
+
+def golden_oracle_runs(name: str) -> list:
+    """Full-size oracle runs of this workload recorded by the golden files
+    (tests/golden/make_golden.py, one host core): same-workload context."""
+    import glob
+    out = []
+    for path in sorted(glob.glob(os.path.join(ROOT, "tests", "golden", f"{name}_*.json"))):
+        try:
+            d = json.load(open(path))
+            trav = d["n_s"] + comb(d["s"], d["r"]) * d["n_s"]
+            out.append({"r": d["r"], "s": d["s"], "oracle_seconds": d["oracle_seconds"],
+                        "traversals_per_s": trav / d["oracle_seconds"], "cores": 1,
+                        "file": os.path.relpath(path, ROOT)})
+        except (KeyError, ValueError, OSError, ZeroDivisionError):
+            continue
+    return out
+
+
+def cpu_baseline(name: str, r: int, s: int, scale: int) -> dict:
+    """The oracle, single-threaded, on a smaller graph of the same generator
+    (a bounded sample of the workload): traversals per second."""
+    import oracle
+    g, what = cpu_sample(name, scale)
     t0 = time.perf_counter()
     d = oracle.decompose(g, r, s)
     dt = time.perf_counter() - t0
@@ -97,10 +152,10 @@ def cpu_baseline(r: int, s: int, scale: int) -> dict:
         "unit": "s-cliques traversed/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"full ({r},{s}) decomposition of R-MAT scale {scale} (n={g.n}, m={g.m}, "
-                   f"n_r={d.n_r}, n_s={d.n_s}) with the same generator and seed, "
-                   f"{dt:.1f} s on one host core"),
+        "sample": (f"full ({r},{s}) decomposition of {what}: n={g.n}, m={g.m}, "
+                   f"n_r={d.n_r}, n_s={d.n_s}, {dt:.1f} s on one host core"),
         "seconds": dt,
+        "full_size_runs": golden_oracle_runs(name),
     }
 
 
@@ -298,69 +353,47 @@ def bench_serve(pool_size: int, count: int, rates: list[float], workers: int) ->
     return out
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rmat18")
-    ap.add_argument("--rs", default="3,4")
-    ap.add_argument("--cpu-scale", type=int, default=12,
-                    help="R-MAT scale of the oracle baseline sample (0: skip)")
-    ap.add_argument("--peel-blocks", type=int, default=0)
-    ap.add_argument("--batch", type=int, default=4096,
-                    help="graphs in the batched-vs-one-by-one comparison (0: skip)")
-    ap.add_argument("--batch-reps", type=int, default=2)
-    ap.add_argument("--serve", type=int, default=64,
-                    help="requests per rate in the serving sweep (0: skip)")
-    ap.add_argument("--serve-pool", type=int, default=64)
-    ap.add_argument("--serve-rates", default="10,100,1000,2000")
-    ap.add_argument("--serve-workers", type=int, default=2)
-    ap.add_argument("--verbose", action="store_true")
-    args = ap.parse_args()
-
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: the decomposition of one graph is not "
-              "sharded across GPUs.", file=sys.stderr)
-        return 2
-    r, s = (int(x) for x in args.rs.split(","))
-
+def measure(name: str, r: int, s: int, steps: int, warmup: int, peel_blocks: int) -> dict:
+    """Decompose one workload `steps` times after `warmup` untimed runs, the
+    CSR already in HBM; throughput, phases, counters and the roofline of the
+    dominant kernel (its duration from HIP events on the library's stream)."""
     import torch
 
     from paper_2306_08623_amd import nucleus
 
-    if not torch.cuda.is_available():
-        print("no GPU visible", file=sys.stderr)
-        return 1
-    g, desc = workload(args.workload)
+    g, desc = workload(name)
     print(f"[bench] {desc}: n={g.n} m={g.m} (r,s)=({r},{s})", file=sys.stderr, flush=True)
-    ctx = nucleus.Context(device=0, peel_blocks=args.peel_blocks)
+    ctx = nucleus.Context(device=0, peel_blocks=peel_blocks)
     torch.cuda.synchronize()
     tu = time.perf_counter()
     ctx.load_csr(g)              # host -> HBM once (with validation); not in value
     ctx.nd_sync()
     upload_s = time.perf_counter() - tu
     ctx.nd_set_rs(r, s)
-    for i in range(args.warmup):
+    retries = 0
+    for i in range(warmup):
         tw = time.perf_counter()
         ctx.nd_decompose()
+        retries += ctx.nd_get_info()["grid_retries"]
         print(f"[bench] warmup {i}: {time.perf_counter() - tw:.3f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     infos = []
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         ctx.nd_decompose()
         infos.append(ctx.nd_get_info())
         print(f"[bench] step {i}: {time.perf_counter() - t0:.3f} s cumulative", file=sys.stderr,
               flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    ctx.close()
+    retries += sum(i["grid_retries"] for i in infos)
+    if retries:
+        print(f"[bench] WARNING: {retries} persistent launches were relaunched on a smaller "
+              "grid (not fully resident)", file=sys.stderr, flush=True)
     info = infos[-1]
     n_s = info["n_s"]
     trav = n_s + comb(s, r) * n_s
-    value = trav * args.steps / wall
-    ms_step = 1000.0 * wall / args.steps
 
     # roofline of the dominant kernel, timed with HIP events on the
     # library's stream around each launch
@@ -374,38 +407,90 @@ def main() -> int:
     else:
         kname, kms, kbytes = "k_count_s4" if s == 4 else "k_count_s3", count_ms, count_bytes
     achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
-    traffic = measured_traffic(kname, args.workload, r, s)
+    traffic = measured_traffic(kname, name, r, s)
     roof = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
             "traffic": traffic, "bytes_per_launch": kbytes, "kernel_ms": round(kms, 4)}
     if traffic:
         roof["traffic_GBps"] = round(traffic / (kms * 1e-3) / 1e9, 1)
+        roof["traffic_over_model"] = round(traffic / kbytes, 2)
+    return {
+        "value": trav * steps / wall,
+        "ms_per_step": 1000.0 * wall / steps,
+        "steps": steps, "warmup": warmup,
+        "config": {"workload": f"{desc}; (r,s)=({r},{s})", "n": g.n, "m": g.m,
+                   "n_r": info["n_r"], "n_s": n_s, "k": info["k"], "rounds": info["rounds"],
+                   "n_int": info["n_int"]},
+        "host_upload_ms": round(upload_s * 1e3, 3),
+        "value_with_host_upload": trav / (wall / steps + upload_s),
+        "phases_ms": {"prep": round(info["ms_prep"], 3), "count": round(info["ms_count"], 3),
+                      "peel": round(info["ms_peel"], 3), "tree": round(info["ms_tree"], 3)},
+        "counters": {k: info[k] for k in ("visits", "decrements", "links", "link_calls", "unites",
+                                           "bucket_scans", "max_outdeg", "orient_rounds")},
+        "grid_retries": retries,
+        "device_bytes": info["device_bytes"],
+        "roofline": roof,
+    }
 
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="chunglu4m")
+    ap.add_argument("--rs", default="3,4")
+    ap.add_argument("--secondary", default="rmat18",
+                    help="a second workload measured the same way ('' to skip)")
+    ap.add_argument("--secondary-steps", type=int, default=3)
+    ap.add_argument("--cpu-scale", type=int, default=8,
+                    help="the oracle baseline runs on the workload's generator at a size "
+                         "reduced by 2^scale (R-MAT: scale lower by this much) (0: skip)")
+    ap.add_argument("--peel-blocks", type=int, default=0)
+    ap.add_argument("--batch", type=int, default=4096,
+                    help="graphs in the batched-vs-one-by-one comparison (0: skip)")
+    ap.add_argument("--batch-reps", type=int, default=2)
+    ap.add_argument("--serve", type=int, default=64,
+                    help="requests per rate in the serving sweep (0: skip)")
+    ap.add_argument("--serve-pool", type=int, default=64)
+    ap.add_argument("--serve-rates", default="10,20,50,100,200,500,1000,2000")
+    ap.add_argument("--serve-workers", type=int, default=2)
+    ap.add_argument("--verbose", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: the decomposition of one graph is not "
+              "sharded across GPUs.", file=sys.stderr)
+        return 2
+    r, s = (int(x) for x in args.rs.split(","))
+
+    import torch
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    head = measure(args.workload, r, s, args.steps, args.warmup, args.peel_blocks)
     out = {
         "metric": f"({r},{s})-nucleus s-cliques traversed/s",
-        "value": value,
+        "value": head["value"],
         "unit": "s-cliques traversed/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": f"{desc}; (r,s)=({r},{s})", "n": g.n, "m": g.m,
-                   "n_r": info["n_r"], "n_s": n_s, "k": info["k"], "rounds": info["rounds"],
-                   "n_int": info["n_int"]},
-        "host_upload_ms": round(upload_s * 1e3, 3),
-        "value_with_host_upload": trav / (wall / args.steps + upload_s),
-        "phases_ms": {"prep": round(info["ms_prep"], 3), "count": round(info["ms_count"], 3),
-                      "peel": round(info["ms_peel"], 3), "tree": round(info["ms_tree"], 3)},
-        "counters": {k: info[k] for k in ("visits", "decrements", "links", "link_calls", "unites",
-                                           "bucket_scans", "max_outdeg", "orient_rounds")},
-        "roofline": roof,
     }
-    ctx.close()
+    for key in ("config", "host_upload_ms", "value_with_host_upload", "phases_ms", "counters",
+                "grid_retries", "device_bytes", "roofline"):
+        out[key] = head[key]
+    if args.secondary:
+        out["secondary"] = measure(args.secondary, r, s, args.secondary_steps, 1,
+                                   args.peel_blocks)
     if args.batch:
         out["batch"] = bench_batch(args.batch, args.batch_reps)
     if args.serve:
@@ -413,7 +498,7 @@ def main() -> int:
                                    [float(x) for x in args.serve_rates.split(",")],
                                    args.serve_workers)
     if args.cpu_scale:
-        out["cpu_baseline"] = cpu_baseline(r, s, args.cpu_scale)
+        out["cpu_baseline"] = cpu_baseline(args.workload, r, s, args.cpu_scale)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -65,6 +65,15 @@ typedef enum nd_mem {
 
 typedef struct nd_ctx nd_ctx;
 
+/* Device memory callbacks. alloc returns `bytes` of device memory of the
+ * context's GPU (at least 256-byte aligned) usable by work queued on
+ * `hip_stream`, or NULL when it cannot (the call then fails with ND_E_OOM);
+ * free gives back a block that alloc returned, with the same size and
+ * stream. `user` is nd_options.alloc_user. The library never frees a block
+ * that queued work may still read: it waits for its stream first. */
+typedef void *(*nd_alloc_fn)(size_t bytes, void *hip_stream, void *user);
+typedef void (*nd_free_fn)(void *ptr, size_t bytes, void *hip_stream, void *user);
+
 typedef struct nd_options {
   int device;             /* HIP device ordinal                               */
   void *hip_stream;       /* hipStream_t to order work on; NULL = null stream */
@@ -74,6 +83,13 @@ typedef struct nd_options {
   uint32_t work_chunk;    /* probe elements per lane task (>=1); 0 = auto     */
   uint64_t watchdog;      /* max peel rounds before ND_E_WATCHDOG; 0 = auto   */
   uint32_t flags;         /* ND_FLAG_* bits                                   */
+  /* Where the context's device workspace comes from: both NULL = hipMalloc /
+   * hipFree; both set = these callbacks (e.g. a framework's caching
+   * allocator, so that it accounts for and reuses the memory); one of the
+   * two alone is ND_E_INVALID_ARG. */
+  nd_alloc_fn alloc;
+  nd_free_fn free;
+  void *alloc_user;
 } nd_options;
 
 /* nd_options.flags: print a line to stderr when a pipeline phase ends, and
@@ -123,10 +139,17 @@ typedef struct nd_info {
   uint64_t hier_visits;   /* TE: s-cliques met by the hierarchy kernel        */
   uint32_t grid_retries;  /* persistent launches repeated with a smaller grid
                              because the first was not fully resident         */
+  uint64_t cascades;      /* EL: link steps run as recursive calls of
+                             Algorithm 5 (links - link_calls)                 */
+  uint64_t cas_retries;   /* failed compare-and-swaps that were retried: the
+                             union of two roots, and the L updates of
+                             Algorithm 5 (EL) / of the hierarchy pass (TE)    */
+  uint64_t device_peak;   /* largest workspace held during this run (bytes)   */
 } nd_info;
 
 /* Create a context on opt->device (opt may be NULL: device 0, null stream,
- * validation on). The context owns every device buffer it allocates. */
+ * validation on). The context owns every device buffer it allocates (through
+ * opt->alloc when set) and releases all of them in nd_destroy. */
 nd_status nd_create(nd_ctx **out, const nd_options *opt);
 void nd_destroy(nd_ctx *ctx);
 
@@ -184,6 +207,42 @@ nd_status nd_get_peel_rounds(nd_ctx *ctx, uint32_t *out, nd_mem where);
 /* Canonical tree: parent uint64[n_r + n_int] (UINT64_MAX for roots) and
  * level uint32[n_int] (level of node n_r + i). Either pointer may be NULL. */
 nd_status nd_get_tree(nd_ctx *ctx, uint64_t *parent, uint32_t *level, nd_mem where);
+
+/* ---- Hierarchy cut: the c-(r,s) nuclei ---------------------------------
+ *
+ * With the hierarchy, the nuclei of any level c come from the tree alone
+ * (Section 8, on the usefulness of the hierarchy): drop every node of level
+ * below c; each remaining maximal subtree is one c-(r,s) nucleus and holds
+ * all of its leaves. Without it one would rerun connected components over
+ * the r-cliques of core >= c. For every nucleus the library also gives the
+ * vertices of its r-cliques and the number of graph edges among them (its
+ * edge density is n_edges / C(n_vertices, 2)). */
+
+typedef struct nd_nucleus {
+  uint64_t node;          /* its canonical tree node (n_r .. n_r + n_int - 1) */
+  uint64_t min_leaf;      /* its smallest r-clique index                      */
+  uint64_t n_rcliques;    /* r-cliques in it (the leaves of its subtree)      */
+  uint64_t n_vertices;    /* distinct vertices of those r-cliques             */
+  uint64_t n_edges;       /* edges of the graph with both ends among them     */
+  uint64_t vert_off;      /* its vertices: verts[vert_off .. + n_vertices)    */
+  uint32_t level;         /* the node's level (>= c): smallest core inside    */
+  uint32_t reserved;
+} nd_nucleus;
+
+/* Cut the tree of the last nd_decompose at level c >= 1 (ND_E_INVALID_ARG
+ * for c = 0; ND_E_STATE without a decomposition, e.g. after a batch).
+ * Computes on the device and waits; *n_nuclei and *n_vertices (either may
+ * be NULL) receive the number of nuclei and the total length of their
+ * vertex lists. c above the maximum core number gives no nucleus. The
+ * result stays on the device until the next decomposition or cut. */
+nd_status nd_cut(nd_ctx *ctx, uint32_t c, uint64_t *n_nuclei, uint64_t *n_vertices);
+
+/* Copy the last cut out (any pointer may be NULL): nuclei[n_nuclei] in
+ * ascending node order; verts[n_vertices], each nucleus's vertex ids
+ * ascending at its vert_off; leaf_nucleus[n_r], the index of the nucleus
+ * holding each r-clique, UINT32_MAX for r-cliques of core below c. */
+nd_status nd_get_cut(nd_ctx *ctx, nd_nucleus *nuclei, uint32_t *verts, uint32_t *leaf_nucleus,
+                     nd_mem where);
 
 /* ---- Batches of independent graphs ------------------------------------
  *
@@ -251,12 +310,12 @@ nd_status nd_estimate_footprint(const nd_graph_desc *g, nd_mem where, uint64_t *
  * share. Each pipeline repeatedly takes every admissible waiting request, up
  * to max_batch, and decomposes them together (nd_batch_decompose), so
  * requests that arrive while others run join the next batch of whichever
- * pipeline frees first. The host work of one pipeline (copies at
- * submission, checks, packing the union) overlaps the device work of
- * another; the device runs one batch at a time, because the persistent
- * grid-barrier kernels need all of their workgroups resident. Results stay in
- * device memory until released. Every result is exactly the one nd_decompose
- * gives for the graph alone. */
+ * pipeline frees first. The pipelines' batches run on the device at the same
+ * time: each pipeline's persistent grid-barrier kernels take 1/workers of the
+ * device, so all of them are resident together, and the other kernels share
+ * what is left (nd_server_stats reports the measured device overlap).
+ * Results stay in device memory until released. Every result is exactly the
+ * one nd_decompose gives for the graph alone. */
 
 typedef struct nd_server nd_server;
 
@@ -326,6 +385,14 @@ typedef struct nd_server_stats {
   uint64_t workspace_share;   /* workspace bytes each pipeline may hold         */
   uint64_t result_share;      /* result bytes the server may hold               */
   uint64_t overlapped;        /* requests admitted while another pipeline ran   */
+  /* device time of the batches run so far (the last 65,536), from HIP events
+   * recorded on each pipeline's stream around its device work: the sum of
+   * the batches' intervals, the time covered by at least one, and the time
+   * covered by at least two (batches of different pipelines overlapping on
+   * the GPU) */
+  double device_batch_ms;
+  double device_busy_ms;
+  double device_overlap_ms;
 } nd_server_stats;
 
 nd_status nd_server_get_stats(nd_server *srv, nd_server_stats *out);

@@ -41,6 +41,21 @@ class _Result(C.Structure):
     ]
 
 
+class _Cut(C.Structure):
+    _fields_ = [
+        ("n_r", C.c_uint64), ("n_nuclei", C.c_uint64),
+        ("leaf_nucleus", C.POINTER(C.c_uint64)),
+        ("min_leaf", C.POINTER(C.c_uint64)),
+        ("level", C.POINTER(C.c_uint64)),
+        ("n_rcliques", C.POINTER(C.c_uint64)),
+        ("n_vertices", C.POINTER(C.c_uint64)),
+        ("n_edges", C.POINTER(C.c_uint64)),
+        ("vert_off", C.POINTER(C.c_uint64)),
+        ("verts", C.POINTER(C.c_uint32)),
+        ("t_cut", C.c_double),
+    ]
+
+
 def build(force: bool = False) -> str:
     """Compile ``libndo.so`` with gcc (portable flags, single-threaded)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
@@ -74,6 +89,11 @@ def _load():
         lib.ndo_open.argtypes = [C.c_uint32, u64p, u32p, C.c_uint32, C.c_uint32,
                                  C.POINTER(C.c_void_p)]
         lib.ndo_open.restype = C.c_int
+        lib.ndo_nuclei.argtypes = [C.c_uint32, u64p, u32p, C.c_uint32, C.c_uint32, u64p,
+                                   C.c_uint64, C.POINTER(_Cut)]
+        lib.ndo_nuclei.restype = C.c_int
+        lib.ndo_cut_free.argtypes = [C.POINTER(_Cut)]
+        lib.ndo_cut_free.restype = None
         lib.ndo_graph_n_r.argtypes = [C.c_void_p]
         lib.ndo_graph_n_r.restype = C.c_uint64
         lib.ndo_graph_rcliques.argtypes = [C.c_void_p, u32p]
@@ -214,3 +234,41 @@ def decompose(csr, r: int, s: int) -> Decomposition:
 def count(csr, r: int, s: int) -> Decomposition:
     """Only r-clique listing and per-r-clique s-clique counts."""
     return _run("ndo_count", csr, r, s, False)
+
+
+def nuclei(csr, r: int, s: int, coreness, c: int) -> dict:
+    """The c-(r,s) nuclei from the definition (components of the r-cliques of
+    core >= c under s-clique adjacency, no tree): per nucleus, numbered by
+    its smallest r-clique id, that id, its level (smallest core inside), its
+    r-clique count, sorted vertex set and the edges of G among those
+    vertices; plus every r-clique's nucleus (-1 = none) and the seconds the
+    query took."""
+    lib = _load()
+    rp, col = _csr_args(csr)
+    core = np.ascontiguousarray(coreness, dtype=np.uint64)
+    if core.size == 0:
+        core = np.zeros(1, dtype=np.uint64)
+    res = _Cut()
+    st = lib.ndo_nuclei(csr.n, rp.ctypes.data_as(C.POINTER(C.c_uint64)),
+                        col.ctypes.data_as(C.POINTER(C.c_uint32)), r, s,
+                        core.ctypes.data_as(C.POINTER(C.c_uint64)), c, C.byref(res))
+    if st != NDO_OK:
+        raise OracleError(st)
+    try:
+        nn, n_r = int(res.n_nuclei), int(res.n_r)
+        off = _arr(res.vert_off, nn + 1, np.uint64) if nn else np.zeros(1, np.uint64)
+        leaf = _arr(res.leaf_nucleus, n_r, np.uint64).astype(np.int64)
+        return {
+            "n_nuclei": nn,
+            "leaf_nucleus": leaf,
+            "min_leaf": _arr(res.min_leaf, nn, np.uint64),
+            "level": _arr(res.level, nn, np.uint64),
+            "n_rcliques": _arr(res.n_rcliques, nn, np.uint64),
+            "n_vertices": _arr(res.n_vertices, nn, np.uint64),
+            "n_edges": _arr(res.n_edges, nn, np.uint64),
+            "vert_off": off,
+            "verts": _arr(res.verts, int(off[-1]), np.uint32),
+            "seconds": float(res.t_cut),
+        }
+    finally:
+        lib.ndo_cut_free(C.byref(res))

@@ -723,6 +723,174 @@ int ndo_decompose(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
   return NDO_OK;
 }
 
+/* ---- the c-(r,s) nuclei from the definition ------------------------------- */
+
+typedef struct {
+  const rtable *T;
+  uint32_t s;
+  uint64_t self;
+  subsets sb;
+  const uint64_t *coreness;
+  uint64_t c;
+  uint64_t *uf;
+} cutter;
+
+/* R and every other r-clique R' of the s-clique S with core >= c are
+ * s-clique-adjacent members of the graph G_c: join them */
+static void emit_cut(const uint32_t *S, void *ctx) {
+  cutter *K = (cutter *)ctx;
+  uint32_t sub[MAXS];
+  for (uint32_t i = 0; i < K->sb.nm; i++) {
+    subset_tuple(S, K->s, K->sb.mask[i], sub);
+    uint64_t id = rlookup(K->T, sub);
+    if (id != K->self && K->coreness[id] >= K->c) uf_union(K->uf, K->self, id);
+  }
+}
+
+static int u64_cmp(const void *a, const void *b) {
+  uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+  return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+void ndo_cut_free(ndo_cut *cut) {
+  if (!cut) return;
+  free(cut->leaf_nucleus);
+  free(cut->min_leaf);
+  free(cut->level);
+  free(cut->n_rcliques);
+  free(cut->n_vertices);
+  free(cut->n_edges);
+  free(cut->vert_off);
+  free(cut->verts);
+  memset(cut, 0, sizeof(*cut));
+}
+
+int ndo_nuclei(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, uint32_t r, uint32_t s,
+               const uint64_t *coreness, uint64_t c, ndo_cut *out) {
+  if (!out) return NDO_E_INVALID_ARG;
+  memset(out, 0, sizeof(*out));
+  if (r < 1 || s <= r || s > MAXS || c < 1 || !coreness) return NDO_E_INVALID_ARG;
+  graph g;
+  int st = build_graph(&g, n, row_ptr, col);
+  if (st != NDO_OK) return st;
+  /* O1: the r-cliques and their lexicographic ids */
+  rcollect rc;
+  memset(&rc, 0, sizeof(rc));
+  rc.r = r;
+  st = list_cliques(&g, r, emit_rcollect, &rc);
+  if (st != NDO_OK || rc.v.oom) { free(rc.v.a); return NDO_E_OOM; }
+  rtable T;
+  T.r = r;
+  T.n_r = rc.v.n / r;
+  T.t = rc.v.a;
+  T.first = (uint64_t *)calloc((uint64_t)n + 1, sizeof(uint64_t));
+  const uint64_t nr = T.n_r, nr1 = nr ? nr : 1;
+  uint64_t *uf = (uint64_t *)malloc(nr1 * sizeof(uint64_t));
+  out->leaf_nucleus = (uint64_t *)malloc(nr1 * sizeof(uint64_t));
+  sscan X;
+  int sst = sscan_init(&X, &g, r, s, emit_cut, NULL);
+  if (!T.first || !uf || !out->leaf_nucleus || sst != NDO_OK) {
+    free(T.t); free(T.first); free(uf); sscan_free(&X); ndo_cut_free(out);
+    return NDO_E_OOM;
+  }
+  for (uint64_t i = 0; i < nr; i++) T.first[T.t[i * r] + 1]++;
+  for (uint32_t a = 0; a < n; a++) T.first[a + 1] += T.first[a];
+  out->n_r = nr;
+  double t0 = now_s();
+
+  /* components of G_c: every s-clique of an r-clique of core >= c joins its
+   * members of core >= c */
+  cutter K;
+  memset(&K, 0, sizeof(K));
+  K.T = &T; K.s = s; K.coreness = coreness; K.c = c; K.uf = uf;
+  make_subsets(&K.sb, r, s);
+  X.ctx = &K;
+  for (uint64_t i = 0; i < nr; i++) uf[i] = i;
+  uint32_t tup[MAXS];
+  for (uint64_t R = 0; R < nr; R++) {
+    if (coreness[R] < c) continue;
+    K.self = R;
+    memcpy(tup, T.t + R * r, r * sizeof(uint32_t));
+    for_each_sclique(&X, tup);
+  }
+  sscan_free(&X);
+
+  /* nuclei numbered by their smallest r-clique: the first member met in
+   * ascending id order names the component */
+  uint64_t nn = 0;
+  uint64_t *comp_of_root = (uint64_t *)malloc(nr1 * sizeof(uint64_t));
+  if (!comp_of_root) { free(T.t); free(T.first); free(uf); ndo_cut_free(out); return NDO_E_OOM; }
+  for (uint64_t i = 0; i < nr; i++) comp_of_root[i] = NONE;
+  for (uint64_t R = 0; R < nr; R++) {
+    out->leaf_nucleus[R] = NONE;
+    if (coreness[R] < c) continue;
+    uint64_t root = uf_find(uf, R);
+    if (comp_of_root[root] == NONE) comp_of_root[root] = nn++;
+    out->leaf_nucleus[R] = comp_of_root[root];
+  }
+  free(comp_of_root);
+  free(uf);
+  out->n_nuclei = nn;
+  uint64_t nn1 = nn ? nn : 1;
+  out->min_leaf = (uint64_t *)malloc(nn1 * sizeof(uint64_t));
+  out->level = (uint64_t *)malloc(nn1 * sizeof(uint64_t));
+  out->n_rcliques = (uint64_t *)calloc(nn1, sizeof(uint64_t));
+  out->n_vertices = (uint64_t *)calloc(nn1, sizeof(uint64_t));
+  out->n_edges = (uint64_t *)calloc(nn1, sizeof(uint64_t));
+  out->vert_off = (uint64_t *)calloc(nn1 + 1, sizeof(uint64_t));
+  /* (nucleus, vertex) pairs of every member r-clique, sorted, duplicates
+   * dropped: the vertex sets */
+  uint64_t np = 0;
+  for (uint64_t R = 0; R < nr; R++) np += out->leaf_nucleus[R] != NONE ? r : 0;
+  uint64_t *pairs = (uint64_t *)malloc((np ? np : 1) * sizeof(uint64_t));
+  if (!out->min_leaf || !out->level || !out->n_rcliques || !out->n_vertices || !out->n_edges ||
+      !out->vert_off || !pairs) {
+    free(pairs); free(T.t); free(T.first); ndo_cut_free(out);
+    return NDO_E_OOM;
+  }
+  for (uint64_t i = 0; i < nn; i++) { out->min_leaf[i] = NONE; out->level[i] = NONE; }
+  np = 0;
+  for (uint64_t R = 0; R < nr; R++) {
+    uint64_t q = out->leaf_nucleus[R];
+    if (q == NONE) continue;
+    if (R < out->min_leaf[q]) out->min_leaf[q] = R;
+    if (coreness[R] < out->level[q]) out->level[q] = coreness[R];
+    out->n_rcliques[q]++;
+    for (uint32_t j = 0; j < r; j++) pairs[np++] = (q << 32) | T.t[R * r + j];
+  }
+  qsort(pairs, np, sizeof(uint64_t), u64_cmp);
+  uint64_t nv = 0;
+  for (uint64_t i = 0; i < np; i++)
+    if (i == 0 || pairs[i] != pairs[i - 1]) pairs[nv++] = pairs[i];
+  out->verts = (uint32_t *)malloc((nv ? nv : 1) * sizeof(uint32_t));
+  if (!out->verts) { free(pairs); free(T.t); free(T.first); ndo_cut_free(out); return NDO_E_OOM; }
+  for (uint64_t i = 0; i < nv; i++) {
+    out->verts[i] = (uint32_t)(pairs[i] & 0xFFFFFFFFu);
+    out->n_vertices[pairs[i] >> 32]++;
+  }
+  free(pairs);
+  for (uint64_t q = 0; q < nn; q++) out->vert_off[q + 1] = out->vert_off[q] + out->n_vertices[q];
+  /* edges of G with both ends in the nucleus's vertex set, each counted
+   * once from its smaller end */
+  for (uint64_t q = 0; q < nn; q++) {
+    const uint32_t *V = out->verts + out->vert_off[q];
+    const uint64_t nvq = out->n_vertices[q];
+    for (uint64_t i = 0; i < nvq; i++) {
+      uint32_t v = V[i];
+      for (uint64_t j = row_ptr[v]; j < row_ptr[v + 1]; j++) {
+        uint32_t w = col[j];
+        if (w <= v) continue;
+        uint64_t p = lower_bound32(V, 0, nvq, w);
+        if (p < nvq && V[p] == w) out->n_edges[q]++;
+      }
+    }
+  }
+  out->t_cut = now_s() - t0;
+  free(T.t);
+  free(T.first);
+  return NDO_OK;
+}
+
 /* ---- per-r-clique queries -------------------------------------------------- */
 
 struct ndo_graph {

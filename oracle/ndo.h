@@ -82,6 +82,31 @@ int ndo_count(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
 
 void ndo_free(ndo_result *res);
 
+/* The c-(r,s) nuclei from the definition (Section 8, on the usefulness of
+ * the hierarchy: without a hierarchy, the nuclei of level c are the
+ * connected components of the r-cliques of core number >= c under s-clique
+ * adjacency, Section 3). No tree is used: the components are found by a
+ * union-find over every s-clique of those r-cliques. `coreness` is indexed
+ * by the canonical r-clique id (as ndo_decompose returns it); c >= 1.
+ * Nuclei are numbered by their smallest r-clique id. */
+typedef struct ndo_cut {
+  uint64_t n_r;
+  uint64_t n_nuclei;
+  uint64_t *leaf_nucleus;  /* n_r: nucleus of each r-clique, UINT64_MAX if core < c */
+  uint64_t *min_leaf;      /* n_nuclei: smallest r-clique id in the nucleus */
+  uint64_t *level;         /* n_nuclei: smallest core number in it */
+  uint64_t *n_rcliques;    /* n_nuclei: its r-cliques */
+  uint64_t *n_vertices;    /* n_nuclei: vertices of its r-cliques */
+  uint64_t *n_edges;       /* n_nuclei: edges of G with both ends among them */
+  uint64_t *vert_off;      /* n_nuclei + 1: its vertices are verts[vert_off[i] ..) */
+  uint32_t *verts;         /* ascending within each nucleus */
+  double t_cut;            /* seconds: components, vertex sets and edges */
+} ndo_cut;
+
+int ndo_nuclei(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, uint32_t r, uint32_t s,
+               const uint64_t *coreness, uint64_t c, ndo_cut *out);
+void ndo_cut_free(ndo_cut *cut);
+
 /* Per-r-clique queries on a graph too large for a full decomposition.
  * ndo_open lists the r-cliques (O1) once; ndo_incident then enumerates the
  * s-cliques containing one r-clique. */

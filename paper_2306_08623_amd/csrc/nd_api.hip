@@ -25,13 +25,48 @@ nd_status nd_hip(nd_ctx *c, hipError_t e, const char *what) {
   return nd_fail(c, ND_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Device memory of a context: its arena, the caller's callbacks, or
+// hipMalloc / hipFree.
+static void *dev_alloc(nd_ctx *c, size_t bytes) {
+  if (c->arena) {
+    const uint64_t at = (c->arena_used + 255) & ~255ull;
+    if (at > c->arena_cap || bytes > c->arena_cap - at) return nullptr;
+    c->arena_used = at + bytes;
+    return c->arena + at;
+  }
+  if (c->alloc_fn) return c->alloc_fn(bytes, (void *)c->stream, c->alloc_user);
+  void *p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+static void dev_free(nd_ctx *c, void *p, size_t bytes) {
+  if (!p || c->arena) return;   // arena memory is reused after nd_arena_reset
+  if (c->free_fn) c->free_fn(p, bytes, (void *)c->stream, c->alloc_user);
+  else (void)hipFree(p);
+}
+
+void nd_arena_reset(nd_ctx *c) {
+  for (auto &b : c->bufs) {
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  c->arena_used = 0;
+  c->bytes_held = 0;
+  c->bytes_peak = 0;
+}
+
 void *nd_buf(nd_ctx *c, int id, size_t bytes, nd_status *st) {
   *st = ND_OK;
   if ((int)c->bufs.size() <= id) c->bufs.resize(std::max(id + 1, (int)B_COUNT));
   DevBuf &b = c->bufs[id];
   if (bytes == 0) bytes = 8;
   if (b.p && b.bytes >= bytes) return b.p;
-  size_t want = std::max<size_t>(bytes, b.bytes + b.bytes / 4);   // grow with slack
+  // grow with slack, except in an arena, where every byte counts
+  size_t want = c->arena ? bytes : std::max<size_t>(bytes, b.bytes + b.bytes / 4);
   uint64_t held_after = c->bytes_held - b.bytes + want;
   if (c->mem_limit && held_after > c->mem_limit) {
     want = bytes;
@@ -43,27 +78,36 @@ void *nd_buf(nd_ctx *c, int id, size_t bytes, nd_status *st) {
     }
   }
   if (b.p) {
-    // the old buffer may still be read by queued kernels
-    hipError_t e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) {
-      *st = nd_hip(c, e, "sync before realloc");
-      return nullptr;
+    if (!c->arena) {
+      // the old buffer may still be read by queued kernels
+      hipError_t e = hipStreamSynchronize(c->stream);
+      if (e != hipSuccess) {
+        *st = nd_hip(c, e, "sync before realloc");
+        return nullptr;
+      }
     }
-    (void)hipFree(b.p);
+    dev_free(c, b.p, b.bytes);
     c->bytes_held -= b.bytes;
     b.p = nullptr;
     b.bytes = 0;
   }
-  void *p = nullptr;
-  hipError_t e = hipMalloc(&p, want);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    *st = nd_fail(c, ND_E_OOM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+  void *p = dev_alloc(c, want);
+  if (!p) {
+    if (c->arena)
+      *st = nd_fail(c, ND_E_OOM,
+                    "the fixed scratch of " + std::to_string(c->arena_cap) +
+                        " bytes is too small for this graph (" + std::to_string(want) +
+                        " more bytes needed at offset " + std::to_string(c->arena_used) + ")");
+    else
+      *st = nd_fail(c, ND_E_OOM,
+                    std::string(c->alloc_fn ? "allocator callback" : "hipMalloc") + " of " +
+                        std::to_string(want) + " bytes failed");
     return nullptr;
   }
   b.p = p;
   b.bytes = want;
   c->bytes_held += want;
+  c->bytes_peak = std::max(c->bytes_peak, c->bytes_held);
   return p;
 }
 
@@ -98,7 +142,7 @@ void nd_report_while_running(nd_ctx *c, const char *phase, const uint32_t *progr
   }
 }
 
-nd_status nd_coop_launch(nd_ctx *c, const void *kern, uint32_t *nb, uint32_t *nb_arg,
+nd_status nd_persistent_launch(nd_ctx *c, const void *kern, uint32_t *nb, uint32_t *nb_arg,
                          dim3 block, void **args, hipEvent_t before, hipEvent_t after,
                          const char *what) {
   DevScalars *sc = (DevScalars *)c->bufs[B_SCAL].p;
@@ -107,7 +151,9 @@ nd_status nd_coop_launch(nd_ctx *c, const void *kern, uint32_t *nb, uint32_t *nb
     nd_status st = nd_hip(c, hipMemsetAsync(sc->bar, 0, sizeof(sc->bar), c->stream), "barrier reset");
     if (st != ND_OK) return st;
     if (before) (void)hipEventRecord(before, c->stream);
-    st = nd_hip(c, hipLaunchCooperativeKernel(kern, dim3(*nb), block, args, 0, c->stream), what);
+    // a plain launch: the kernel's own residency gate checks that all of
+    // its workgroups run at once (see nd_internal.h)
+    st = nd_hip(c, hipLaunchKernel(kern, dim3(*nb), block, args, 0, c->stream), what);
     if (after) (void)hipEventRecord(after, c->stream);
     if (st != ND_OK) return st;
     if (c->report_phase && c->progress) nd_report_while_running(c, c->report_phase, c->progress);
@@ -125,7 +171,8 @@ nd_status nd_coop_launch(nd_ctx *c, const void *kern, uint32_t *nb, uint32_t *nb
       }
       return ND_OK;
     }
-    // not resident: nothing was written before the gate; clear and shrink
+    // not resident: no workgroup got past the gate's barrier, so nothing
+    // was written; clear the status and shrink
     c->info.grid_retries++;
     nd_report(c, "%s: grid of %u workgroups not resident, retrying smaller", what, *nb);
     const uint32_t zero = 0;
@@ -187,6 +234,14 @@ nd_status nd_create(nd_ctx **out, const nd_options *opt) {
     c->work_chunk = opt->work_chunk;
     c->watchdog = opt->watchdog;
     c->flags = opt->flags;
+    if ((opt->alloc == nullptr) != (opt->free == nullptr)) {
+      g_create_error = "nd_options.alloc and nd_options.free must be given together";
+      delete c;
+      return ND_E_INVALID_ARG;
+    }
+    c->alloc_fn = opt->alloc;
+    c->free_fn = opt->free;
+    c->alloc_user = opt->alloc_user;
   }
   g_create_error.clear();
   int ndev = 0;
@@ -206,11 +261,6 @@ nd_status nd_create(nd_ctx **out, const nd_options *opt) {
       c->cu_count <= 0)
     return create_fail(c, ND_E_DEVICE,
                        std::string("compute unit count: ") + hipGetErrorString(e));
-  int coop = 0;
-  if ((e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device)) !=
-          hipSuccess ||
-      !coop)
-    return create_fail(c, ND_E_UNSUPPORTED, "the device does not support cooperative launches");
   c->bufs.resize(B_COUNT);
   if (c->flags & ND_FLAG_PROGRESS) {
     if (hipHostMalloc((void **)&c->progress, 16, hipHostMallocDefault) != hipSuccess) {
@@ -238,7 +288,7 @@ void nd_destroy(nd_ctx *c) {
   (void)hipStreamSynchronize(c->stream);
   nd_batch_release(c);
   for (auto &b : c->bufs)
-    if (b.p) (void)hipFree(b.p);
+    if (b.p) dev_free(c, b.p, b.bytes);
   for (int i = 0; i < 10; i++)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
   if (c->progress) (void)hipHostFree(c->progress);
@@ -252,6 +302,7 @@ nd_status nd_load_csr(nd_ctx *c, uint32_t n, uint64_t nnz, const uint64_t *row_p
   if (st != ND_OK) return st;
   c->have_graph = false;
   c->decomposed = false;
+  c->cut_valid = false;
   c->info_valid = false;
   if (!row_ptr || (nnz && !col)) return nd_fail(c, ND_E_INVALID_ARG, "NULL row_ptr or col");
   if (where != ND_MEM_HOST && where != ND_MEM_DEVICE)
@@ -324,8 +375,10 @@ static nd_status check_device_status(nd_ctx *c, DevScalars *host) {
 nd_status nd_run_pipeline(nd_ctx *c) {
   nd_status st;
   c->decomposed = false;
+  c->cut_valid = false;
   c->info_valid = false;
   memset(&c->info, 0, sizeof(c->info));
+  c->bytes_peak = c->bytes_held;
   DevScalars *sc = (DevScalars *)c->bufs[B_SCAL].p;
   if ((st = nd_hip(c, hipMemsetAsync(sc, 0, sizeof(DevScalars), c->stream), "scalars")) != ND_OK)
     return st;
@@ -370,6 +423,9 @@ nd_status nd_run_pipeline(nd_ctx *c) {
   I.hier_visits = hs.hier_visits;
   I.orient_rounds = hs.orient_round;
   I.device_bytes = c->bytes_held;
+  I.device_peak = c->bytes_peak;
+  I.cas_retries = hs.cas_retries;
+  I.cascades = (!I.hier_te && hs.links > hs.link_calls) ? hs.links - hs.link_calls : 0;
   if (c->events_ok) {
     float ms = 0;
     if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) I.ms_prep = ms;

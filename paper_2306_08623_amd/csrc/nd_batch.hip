@@ -413,6 +413,9 @@ static void add_info(nd_info &T, const nd_info &I) {
   T.ms_hier += I.ms_hier;
   T.hier_visits += I.hier_visits;
   T.grid_retries += I.grid_retries;
+  T.cascades += I.cascades;
+  T.cas_retries += I.cas_retries;
+  T.device_peak = std::max(T.device_peak, I.device_peak);
 }
 
 // Host half of a batch: checks, grouping by (r,s) and, for host inputs, the

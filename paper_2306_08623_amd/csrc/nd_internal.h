@@ -209,7 +209,7 @@ constexpr uint32_t kBarGroup0 = 3 * kBarLine;
 constexpr uint32_t kBarWords = kBarGroup0 + kBarGroups * kBarLine;
 
 // Grid-wide barrier for a persistent launch whose workgroups are all
-// resident (cooperative launch). Arrivals are counted per group (monotone
+// resident (checked by residency_gate at the kernel's start). Arrivals are counted per group (monotone
 // counters: a workgroup's generation is its arrival index over the group's
 // size); the last arrival of a group counts the group done, and the last
 // group publishes the generation, which every workgroup waits for. Fences:
@@ -258,9 +258,14 @@ __device__ __forceinline__ bool grid_barrier(uint64_t *bar, uint32_t nblocks, ui
 
 // First step of every persistent (grid-barrier) kernel, before it touches
 // any state: all workgroups must arrive within 200 ms, else the grid is not
-// fully resident (the device cannot run all of its workgroups at once) and
-// every workgroup leaves with ND_DERR_RESIDENCY, so that the host relaunches
-// a smaller grid instead of the barriers waiting out their watchdog.
+// fully resident (the device cannot run all of its workgroups at once, or
+// other work holds part of it) and every workgroup leaves with
+// ND_DERR_RESIDENCY, so that the host relaunches a smaller grid instead of
+// the barriers waiting out their watchdog. A workgroup can see the last
+// arrival just as another one gives up waiting; a grid barrier after the
+// gate therefore lets the kernel go on only when every workgroup passed it
+// (one that gave up never arrives there, and its status bit releases the
+// others), so a grid that will be relaunched has written nothing.
 constexpr uint64_t kResidencyTicks = 20000000ull;
 
 __device__ __forceinline__ bool residency_gate(uint64_t *bar, uint32_t nblocks,
@@ -284,7 +289,8 @@ __device__ __forceinline__ bool residency_gate(uint64_t *bar, uint32_t nblocks,
     s_in = ok;
   }
   __syncthreads();
-  return s_in != 0;
+  if (s_in == 0) return false;
+  return grid_barrier(bar, nblocks, status);
 }
 
 // ---------------------------------------------------------------------------
@@ -307,6 +313,9 @@ struct nd_ctx {
   uint32_t work_chunk = 0;
   uint64_t watchdog = 0;
   uint32_t flags = 0;          // ND_FLAG_*
+  // persistent grids take 1/grid_div of the device, so that as many
+  // pipelines' persistent kernels fit on it at once (the server's workers)
+  uint32_t grid_div = 1;
   uint32_t *progress = nullptr;   // pinned host words the peel kernel updates
   const char *report_phase = nullptr;   // name of the running persistent launch
   // largest grid of each persistent kernel found resident on this device
@@ -325,9 +334,18 @@ struct nd_ctx {
   // results of the last nd_batch_decompose (nd_batch.hip)
   BatchState *batch = nullptr;
 
+  // device memory: hipMalloc / hipFree, the caller's callbacks, or a fixed
+  // arena (sub-allocated in order, released all at once by nd_arena_reset)
+  nd_alloc_fn alloc_fn = nullptr;
+  nd_free_fn free_fn = nullptr;
+  void *alloc_user = nullptr;
+  char *arena = nullptr;
+  uint64_t arena_cap = 0, arena_used = 0;
+
   // named device buffers (grow-only)
   std::vector<DevBuf> bufs;
   uint64_t bytes_held = 0;
+  uint64_t bytes_peak = 0;   // largest bytes_held since the run started
 
   // device views of the prepared tables (valid after a decomposition)
   GraphView gv{};
@@ -336,6 +354,9 @@ struct nd_ctx {
   nd_info info{};
   uint64_t n_r = 0;
   uint64_t n_int = 0;
+  // last hierarchy cut (nd_cut): valid until the next decomposition
+  bool cut_valid = false;
+  uint64_t cut_nuclei = 0, cut_verts = 0;
 
   // events for phase timing: 0 start, 1 prep, 2 count, 3 peel, 4 tree;
   // 5/6 around the peel kernel, 7/8 around the count kernel
@@ -354,6 +375,9 @@ enum BufId : int {
   B_SORTK0, B_SORTK1, B_SORTV0, B_SORTV1, B_HIST,
   B_PARENT, B_LEVEL, B_RCL, B_GCACHE, B_ACNT, B_NODEML, B_SORTOFF,
   B_BATCHDESC, B_WG, B_W24L, B_LHIST, B_LOFF, B_SG, B_TSEL, B_TG, B_PSTATE,
+  // hierarchy cut (nd_cut.hip)
+  B_CUT_TOP, B_CUT_POS, B_CUT_LEAF, B_CUT_NUC, B_CUT_RCL, B_CUT_K0, B_CUT_K1, B_CUT_V0,
+  B_CUT_V1, B_CUT_FLAG, B_CUT_POS2, B_CUT_VERTS, B_CUT_VNUC, B_CUT_CNT,
   B_COUNT
 };
 
@@ -387,6 +411,7 @@ struct DevScalars {
   uint64_t bucket_scans;
   uint64_t link_calls;     // link calls issued after the redundancy filter
   uint64_t hier_visits;    // s-cliques found by the descending-core hierarchy pass
+  uint64_t cas_retries;    // compare-and-swaps of unite / L that lost a race
   uint32_t status;         // ND_DERR_* bits
   uint32_t k;              // final level reached
   uint32_t rounds;         // peel rounds executed
@@ -404,14 +429,17 @@ struct DevScalars {
 // helpers implemented in nd_api.hip
 nd_status nd_fail(nd_ctx *c, nd_status st, const std::string &msg);
 void *nd_buf(nd_ctx *c, int id, size_t bytes, nd_status *st);
+// forgets every buffer of an arena context (its memory is reused from the
+// start by the next nd_buf calls); the caller ensures no queued work uses it
+void nd_arena_reset(nd_ctx *c);
 nd_status nd_hip(nd_ctx *c, hipError_t e, const char *what);
 
-// Cooperative (grid-barrier) launch of a kernel that opens with
+// Launch of a persistent (grid-barrier) kernel that opens with
 // residency_gate: *nb workgroups (the kernel reads the count from *nb_arg),
 // the barrier counter reset first; if the grid turns out not to be resident
 // it is relaunched with 3/4 of the workgroups (waits for the launch).
 // `before` / `after` (may be null) are recorded around the last attempt.
-nd_status nd_coop_launch(nd_ctx *c, const void *kern, uint32_t *nb, uint32_t *nb_arg,
+nd_status nd_persistent_launch(nd_ctx *c, const void *kern, uint32_t *nb, uint32_t *nb_arg,
                          dim3 block, void **args, hipEvent_t before, hipEvent_t after,
                          const char *what);
 

@@ -1,6 +1,6 @@
 // nd_peel.hip -- peeling rounds interleaved with hierarchy linking
 // (Algorithm 3, Section 7.1, with LINK-EFFICIENT of Algorithm 5,
-// Section 7.3), as one persistent cooperative launch.
+// Section 7.3), as one persistent launch.
 //
 // Round t at level k:
 //   bucket  When the frontier is empty, the remaining r-cliques are scanned
@@ -120,15 +120,23 @@ __device__ __forceinline__ void uf_find2(uint32_t *uf, uint32_t &x, uint32_t &y)
   }
 }
 
+// Counts one compare-and-swap that lost a race and is retried (rare: a
+// global atomic only on that path).
+__device__ __forceinline__ void count_retry(uint64_t *retries) {
+  if (retries) atomicAdd((unsigned long long *)retries, 1ull);
+}
+
 // Joins the sets of a and b; the smaller root id survives. Returns the root
 // whose parent pointer this call changed (the loser), or ND_NONE when a and b
-// were already in one set.
-__device__ __forceinline__ uint32_t uf_unite(uint32_t *uf, uint32_t a, uint32_t b) {
+// were already in one set. Lost races are counted into *retries (if given).
+__device__ __forceinline__ uint32_t uf_unite(uint32_t *uf, uint32_t a, uint32_t b,
+                                             uint64_t *retries = nullptr) {
   for (;;) {
     uf_find2(uf, a, b);
     if (a == b) return ND_NONE;
     if (a > b) { uint32_t t = a; a = b; b = t; }
     if (cas32(&uf[b], b, a)) return b;
+    count_retry(retries);
   }
 }
 
@@ -182,7 +190,7 @@ __device__ __forceinline__ uint32_t link_step(LinkCtx &c, uint32_t R, uint32_t Q
   }
   if (ndR == ndQ) {
     if (R == Q) return 0;
-    const uint32_t loser = uf_unite(c.uf, R, Q);   // hand-over as in link_efficient
+    const uint32_t loser = uf_unite(c.uf, R, Q, &c.sc->cas_retries);   // hand-over as in link_efficient
     if (loser != ND_NONE) {
       c.unites++;
       const uint32_t w = uf_find(c.uf, loser);
@@ -203,6 +211,7 @@ __device__ __forceinline__ uint32_t link_step(LinkCtx &c, uint32_t R, uint32_t Q
         if (pQ != Q) push(R, pQ);
         return no;
       }
+      count_retry(&c.sc->cas_retries);
       continue;
     }
     if (c.nd[LQ] < ndR) {
@@ -212,6 +221,7 @@ __device__ __forceinline__ uint32_t link_step(LinkCtx &c, uint32_t R, uint32_t Q
         push(R, LQ);
         return no;
       }
+      count_retry(&c.sc->cas_retries);
     } else {
       push(R, LQ);
       return no;
@@ -307,7 +317,7 @@ __device__ void link_efficient(LinkCtx &c, uint32_t R0, uint32_t Q0) {
       // case unite joins their current roots, and it is one of those whose L
       // must move (a CAS on L[loser] that lands after this read is handed
       // over by its own writer, which then sees loser is no longer a root).
-      const uint32_t loser = uf_unite(c.uf, R, Q);
+      const uint32_t loser = uf_unite(c.uf, R, Q, &c.sc->cas_retries);
       if (loser != ND_NONE) {
         c.unites++;
         const uint32_t w = uf_find(c.uf, loser);
@@ -332,6 +342,7 @@ __device__ void link_efficient(LinkCtx &c, uint32_t R0, uint32_t Q0) {
             if (pQ != Q) push(R, pQ);   // Q was merged meanwhile
             break;
           }
+          count_retry(&c.sc->cas_retries);
           continue;                      // L[Q] was set concurrently: read again
         }
         if (c.nd[LQ] < ndR) {
@@ -341,6 +352,7 @@ __device__ void link_efficient(LinkCtx &c, uint32_t R0, uint32_t Q0) {
             push(R, LQ);
             break;
           }
+          count_retry(&c.sc->cas_retries);
         } else {
           push(R, LQ);
           break;
@@ -1108,27 +1120,27 @@ __device__ __forceinline__ void hier_pair(const HierArgs &a, uint32_t R, uint32_
                                           uint64_t &unites) {
   const uint32_t n2 = a.nd[R2];
   if (n2 == c) {   // same core: one component, one tree
-    unites += uf_unite(a.uf, R, R2) != ND_NONE;
-    uf_unite(a.tuf, R, R2);
+    unites += uf_unite(a.uf, R, R2, &a.sc->cas_retries) != ND_NONE;
+    uf_unite(a.tuf, R, R2, &a.sc->cas_retries);
     return;
   }
   const uint32_t T = uf_find(a.tuf, R2);
   const uint32_t B = ld_acq32(&a.bottom[T]);
   if (a.nd[B] == c) {   // R2's tree already hangs below a core-c component
-    unites += uf_unite(a.uf, B, R) != ND_NONE;
-    uf_unite(a.tuf, T, R);
+    unites += uf_unite(a.uf, B, R, &a.sc->cas_retries) != ND_NONE;
+    uf_unite(a.tuf, T, R, &a.sc->cas_retries);
     return;
   }
   // R2's tree still ends at a component of a higher core: hang it below R
   const uint32_t Bs = uf_find(a.uf, B);   // final: that core is finished
   const uint32_t old = atomicCAS(&a.L[Bs], ND_NONE, R);
   if (old == ND_NONE) {
-    uf_unite(a.tuf, T, R);
+    uf_unite(a.tuf, T, R, &a.sc->cas_retries);
     const uint32_t w = uf_find(a.tuf, R);
     __hip_atomic_store(&a.bottom[w], R, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   } else {   // taken at this level by the component of `old`
-    unites += uf_unite(a.uf, old, R) != ND_NONE;
-    uf_unite(a.tuf, T, R);
+    unites += uf_unite(a.uf, old, R, &a.sc->cas_retries) != ND_NONE;
+    uf_unite(a.tuf, T, R, &a.sc->cas_retries);
   }
 }
 
@@ -1289,7 +1301,7 @@ uint32_t coop_grid(nd_ctx *c, K kern, uint32_t *nb) {
   } else {
     (void)hipGetLastError();
   }
-  uint64_t cap = (uint64_t)per_cu * (uint64_t)c->cu_count;
+  uint64_t cap = std::max<uint64_t>(1, (uint64_t)per_cu * (uint64_t)c->cu_count / c->grid_div);
   for (const auto &e : c->resident_cap)
     if (e.first == (const void *)kern) cap = std::min<uint64_t>(cap, e.second);
   cap = std::min<uint64_t>(cap, kMaxPeelBlocks);
@@ -1306,7 +1318,7 @@ nd_status launch_peel(nd_ctx *c, PeelArgs &pa) {
     return nd_fail(c, ND_E_DEVICE, "occupancy query failed for the peel kernel");
   void *args[] = {&pa};
   if (pa.progress) c->report_phase = "peel";
-  nd_status st = nd_coop_launch(c, kern, &nb, &pa.nblocks, dim3(kPeelBlock), args,
+  nd_status st = nd_persistent_launch(c, kern, &nb, &pa.nblocks, dim3(kPeelBlock), args,
                                 c->events_ok ? c->ev[5] : nullptr,
                                 c->events_ok ? c->ev[6] : nullptr, "peel launch");
   c->report_phase = nullptr;
@@ -1366,7 +1378,7 @@ nd_status run_te(nd_ctx *c, PeelArgs &pa) {
     return nd_fail(c, ND_E_DEVICE, "occupancy query failed for the hierarchy kernel");
   void *args[] = {&h};
   if (h.progress) c->report_phase = "hierarchy";
-  st = nd_coop_launch(c, (const void *)k_hier<R_, S_>, &nb, &h.nblocks, dim3(kPeelBlock), args,
+  st = nd_persistent_launch(c, (const void *)k_hier<R_, S_>, &nb, &h.nblocks, dim3(kPeelBlock), args,
                       nullptr, c->events_ok ? c->ev[9] : nullptr, "hierarchy launch");
   c->report_phase = nullptr;
   return st;

@@ -628,7 +628,9 @@ static uint32_t coop_blocks(nd_ctx *c, const void *kernel, uint32_t block, uint3
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess ||
       per_cu < 1)
     per_cu = 1;
-  uint64_t cap = (uint64_t)per_cu * (uint64_t)c->cu_count;
+  uint64_t cap = std::max<uint64_t>(1, (uint64_t)per_cu * (uint64_t)c->cu_count / c->grid_div);
+  for (const auto &e : c->resident_cap)
+    if (e.first == kernel) cap = std::min<uint64_t>(cap, e.second);
   uint64_t g = want ? std::min<uint64_t>(want, cap) : cap;
   return (uint32_t)std::max<uint64_t>(1, g);
 }
@@ -701,7 +703,7 @@ nd_status nd_stage_prep(nd_ctx *c, GraphView *gv) {
     uint32_t nb = coop_blocks(c, (const void *)k_orient, kOrientBlock,
                               (uint32_t)std::min<uint64_t>(2048, (n + kOrientBlock - 1) / kOrientBlock));
     void *args[] = {&oa};
-    st = nd_coop_launch(c, (const void *)k_orient, &nb, &oa.nblocks, dim3(kOrientBlock), args,
+    st = nd_persistent_launch(c, (const void *)k_orient, &nb, &oa.nblocks, dim3(kOrientBlock), args,
                         nullptr, nullptr, "orientation launch");
     if (st != ND_OK) return st;
   }

@@ -5,9 +5,12 @@
 // free takes every admissible request at the head of the FIFO (up to
 // max_batch) and decomposes them as one batch; requests arriving meanwhile
 // wait for the next free pipeline, so batches form continuously from what
-// has arrived. The pipelines' host work (copies at submission, checks,
-// union packing, admission) overlaps the device work of another pipeline;
-// the device itself runs one batch at a time. Admission uses the footprint estimate of nd_estimate_footprint:
+// has arrived. The pipelines run on the device at the same time: each
+// one's persistent (grid-barrier) kernels take 1/workers of the device, so
+// that all of them fit at once, and the ordinary kernels of one pipeline
+// fill whatever the others leave free. The device intervals of every batch
+// are taken from HIP events, so the overlap is measured, not assumed.
+// Admission uses the footprint estimate of nd_estimate_footprint:
 // a pipeline's batch stays within its workspace share, and the results held
 // on the device (until the client releases them) stay within the result
 // share. Results live in stream-ordered device allocations, so releasing
@@ -25,6 +28,7 @@
 namespace {
 
 constexpr uint64_t kBatchConstBytes = 4ull << 20;   // per-batch fixed workspace
+constexpr size_t kMaxIntervals = 1u << 16;          // batch device intervals kept
 
 using Clock = std::chrono::steady_clock;
 
@@ -93,10 +97,11 @@ struct nd_server {
   std::vector<nd_ctx *> ctxs;
   std::vector<hipStream_t> streams;
   hipStream_t io = nullptr;  // copies out and frees
-  // device work runs one batch at a time: the persistent grid-barrier
-  // kernels need every workgroup resident, so nothing else of the server may
-  // occupy the compute units beside them
-  std::mutex device_mu;
+  // device time of every batch: events recorded on the pipeline's stream
+  // around its device work, read against one reference event
+  hipEvent_t ev_ref = nullptr;
+  std::vector<hipEvent_t> ev_begin, ev_end;
+  std::vector<std::pair<float, float>> intervals;   // ms after ev_ref, last kMaxIntervals
   Clock::time_point t0;
   nd_server_stats stats{};
   std::string last_error;
@@ -131,7 +136,8 @@ void run_batch(nd_server *S, uint32_t w, std::vector<Request *> &batch) {
   BatchState *plan = nullptr;
   std::string err;
   nd_status st = nd_batch_plan(G, descs.data(), ND_MEM_HOST, results.data(), &plan, &err);
-  std::unique_lock<std::mutex> dev(S->device_mu);
+  const bool timed = S->ev_begin[w] && S->ev_end[w];
+  if (timed) (void)hipEventRecord(S->ev_begin[w], c->stream);
   if (st == ND_OK) {
     st = nd_batch_execute(c, plan, descs.data(), results.data());
     err = c->last_error;
@@ -140,7 +146,6 @@ void run_batch(nd_server *S, uint32_t w, std::vector<Request *> &batch) {
     // one member's error (a bad graph, or an estimate too small for the
     // union) fails the whole union: run the members one by one so that only
     // the faulty one fails
-    dev.unlock();
     for (uint32_t i = 0; i < G; i++) {
       std::vector<Request *> one{batch[i]};
       run_batch(S, w, one);
@@ -148,7 +153,6 @@ void run_batch(nd_server *S, uint32_t w, std::vector<Request *> &batch) {
     return;
   }
   if (st != ND_OK) {
-    dev.unlock();
     for (Request *q : batch) q->info.status = st;
     std::lock_guard<std::mutex> lk(S->mu);
     S->last_error = err;
@@ -186,6 +190,43 @@ void run_batch(nd_server *S, uint32_t w, std::vector<Request *> &batch) {
     q->info.status = nd_batch_get(c, i, q->d_rcl, q->d_cnt, q->d_core, q->d_parent, q->d_level,
                                   ND_MEM_DEVICE);
     q->info.result_bytes = bytes;
+  }
+  if (timed) {
+    float a = 0, b = 0;
+    if (hipEventRecord(S->ev_end[w], c->stream) == hipSuccess &&
+        hipEventSynchronize(S->ev_end[w]) == hipSuccess &&
+        hipEventElapsedTime(&a, S->ev_ref, S->ev_begin[w]) == hipSuccess &&
+        hipEventElapsedTime(&b, S->ev_ref, S->ev_end[w]) == hipSuccess) {
+      std::lock_guard<std::mutex> lk(S->mu);
+      if (S->intervals.size() >= kMaxIntervals) S->intervals.erase(S->intervals.begin());
+      S->intervals.emplace_back(a, b);
+    } else {
+      (void)hipGetLastError();
+    }
+  }
+}
+
+// Device time covered by at least one batch, by at least two, and in total
+// (ms), from the recorded intervals.
+void device_overlap(const std::vector<std::pair<float, float>> &iv, double *any, double *two,
+                    double *sum) {
+  std::vector<std::pair<double, int>> ev;
+  *sum = 0;
+  for (const auto &x : iv) {
+    if (x.second <= x.first) continue;
+    ev.emplace_back(x.first, +1);
+    ev.emplace_back(x.second, -1);
+    *sum += x.second - x.first;
+  }
+  std::sort(ev.begin(), ev.end());
+  *any = *two = 0;
+  int depth = 0;
+  double last = 0;
+  for (const auto &e : ev) {
+    if (depth >= 1) *any += e.first - last;
+    if (depth >= 2) *two += e.first - last;
+    depth += e.second;
+    last = e.first;
   }
 }
 
@@ -336,6 +377,21 @@ nd_status nd_server_create(nd_server **out, const nd_server_options *opt) {
     delete S;
     return ND_E_DEVICE;
   }
+  S->ev_begin.assign(S->workers, nullptr);
+  S->ev_end.assign(S->workers, nullptr);
+  if (hipEventCreate(&S->ev_ref) != hipSuccess || hipEventRecord(S->ev_ref, S->io) != hipSuccess ||
+      hipEventSynchronize(S->ev_ref) != hipSuccess) {
+    (void)hipGetLastError();
+    nd_server_destroy(S);
+    return ND_E_DEVICE;
+  }
+  for (uint32_t w = 0; w < S->workers; w++)
+    if (hipEventCreate(&S->ev_begin[w]) != hipSuccess ||
+        hipEventCreate(&S->ev_end[w]) != hipSuccess) {
+      (void)hipGetLastError();
+      nd_server_destroy(S);
+      return ND_E_DEVICE;
+    }
   for (uint32_t w = 0; w < S->workers; w++) {
     hipStream_t st = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
@@ -355,6 +411,7 @@ nd_status nd_server_create(nd_server **out, const nd_server_options *opt) {
       nd_server_destroy(S);
       return rc;
     }
+    c->grid_div = S->workers;   // every pipeline's persistent grids fit at once
     S->ctxs.push_back(c);
   }
   for (uint32_t w = 0; w < S->workers; w++) S->threads.emplace_back(worker_loop, S, w);
@@ -377,6 +434,11 @@ void nd_server_destroy(nd_server *S) {
   }
   if (S->io) (void)hipStreamSynchronize(S->io);
   for (nd_ctx *c : S->ctxs) nd_destroy(c);
+  for (hipEvent_t e : S->ev_begin)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : S->ev_end)
+    if (e) (void)hipEventDestroy(e);
+  if (S->ev_ref) (void)hipEventDestroy(S->ev_ref);
   for (hipStream_t st : S->streams) (void)hipStreamDestroy(st);
   if (S->io) (void)hipStreamDestroy(S->io);
   delete S;
@@ -581,6 +643,8 @@ nd_status nd_server_get_stats(nd_server *S, nd_server_stats *out) {
   if (!S || !out) return ND_E_INVALID_ARG;
   std::lock_guard<std::mutex> lk(S->mu);
   *out = S->stats;
+  device_overlap(S->intervals, &out->device_busy_ms, &out->device_overlap_ms,
+                 &out->device_batch_ms);
   return ND_OK;
 }
 

@@ -1,7 +1,7 @@
 // nd_profile -- runs the decomposition through the C ABI from a plain C++
 // program (no Python, no PyTorch), for profilers that must own the process.
 //
-//   nd_profile <graph.csr> <r> <s> [steps] [work_chunk] [peel_blocks]
+//   nd_profile <graph.csr> <r> <s> [steps] [work_chunk] [peel_blocks] [el|te]
 //
 // The graph file is the binary CSR written by inputs.save_csr():
 // uint32 n, uint64 nnz, uint64 row_ptr[n+1], uint32 col[nnz] (little endian).
@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
+#include <string>
 #include <vector>
 
 #include "nucleus.h"
@@ -22,6 +23,7 @@ int main(int argc, char **argv) {
   const int steps = argc > 4 ? std::atoi(argv[4]) : 1;
   const uint32_t chunk = argc > 5 ? (uint32_t)std::atoi(argv[5]) : 0;
   const uint32_t blocks = argc > 6 ? (uint32_t)std::atoi(argv[6]) : 0;
+  const std::string mode = argc > 7 ? argv[7] : "";
   FILE *f = std::fopen(argv[1], "rb");
   if (!f) {
     std::perror("open");
@@ -40,6 +42,8 @@ int main(int argc, char **argv) {
   opt.validate = 1;
   opt.work_chunk = chunk;
   opt.peel_blocks = blocks;
+  if (mode == "el") opt.flags |= ND_FLAG_HIER_EL;
+  if (mode == "te") opt.flags |= ND_FLAG_HIER_TE;
   nd_status st = nd_create(&ctx, &opt);
   if (st != ND_OK) {
     std::fprintf(stderr, "nd_create: %s (%s)\n", nd_status_str(st), nd_last_error(nullptr));
@@ -52,12 +56,14 @@ int main(int argc, char **argv) {
     nd_info info;
     if (st == ND_OK && (st = nd_get_info(ctx, &info)) == ND_OK)
       std::printf("step %d: n_r=%llu n_s=%llu k=%u rounds=%u prep=%.3f count=%.3f peel=%.3f "
-                  "tree=%.3f ms (count kernel %.3f, peel kernel %.3f) link_calls=%llu "
-                  "link_steps=%llu n_int=%llu\n",
+                  "tree=%.3f ms (count kernel %.3f, peel kernel %.3f, hierarchy %.3f) "
+                  "link_calls=%llu link_steps=%llu cas_retries=%llu grid_retries=%u "
+                  "n_int=%llu\n",
                   i, (unsigned long long)info.n_r, (unsigned long long)info.n_s, info.k,
                   info.rounds, info.ms_prep, info.ms_count, info.ms_peel, info.ms_tree,
-                  info.ms_count_kernel, info.ms_peel_kernel,
+                  info.ms_count_kernel, info.ms_peel_kernel, info.ms_hier,
                   (unsigned long long)info.link_calls, (unsigned long long)info.links,
+                  (unsigned long long)info.cas_retries, info.grid_retries,
                   (unsigned long long)info.n_int);
     std::fflush(stdout);
   }

@@ -52,6 +52,7 @@ EXPORTS = [
     "nd_server_create", "nd_server_destroy", "nd_server_submit", "nd_server_poll",
     "nd_server_wait", "nd_server_get", "nd_server_release", "nd_server_cancel",
     "nd_server_get_stats", "nd_server_last_error",
+    "nd_cut", "nd_get_cut",
     "nd_status_str", "nd_last_error",
 ]
 
@@ -66,6 +67,9 @@ class Options(C.Structure):
         ("work_chunk", C.c_uint32),
         ("watchdog", C.c_uint64),
         ("flags", C.c_uint32),
+        ("alloc", C.c_void_p),
+        ("free", C.c_void_p),
+        ("alloc_user", C.c_void_p),
     ]
 
 
@@ -97,10 +101,26 @@ class Info(C.Structure):
         ("ms_hier", C.c_float),
         ("hier_visits", C.c_uint64),
         ("grid_retries", C.c_uint32),
+        ("cascades", C.c_uint64),
+        ("cas_retries", C.c_uint64),
+        ("device_peak", C.c_uint64),
     ]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class Nucleus(C.Structure):
+    _fields_ = [
+        ("node", C.c_uint64), ("min_leaf", C.c_uint64), ("n_rcliques", C.c_uint64),
+        ("n_vertices", C.c_uint64), ("n_edges", C.c_uint64), ("vert_off", C.c_uint64),
+        ("level", C.c_uint32), ("reserved", C.c_uint32),
+    ]
+
+
+NUCLEUS_DTYPE = np.dtype([("node", "<u8"), ("min_leaf", "<u8"), ("n_rcliques", "<u8"),
+                          ("n_vertices", "<u8"), ("n_edges", "<u8"), ("vert_off", "<u8"),
+                          ("level", "<u4"), ("reserved", "<u4")])
 
 
 class GraphDesc(C.Structure):
@@ -157,10 +177,34 @@ class RequestInfo(C.Structure):
 class ServerStats(C.Structure):
     _fields_ = [(name, C.c_uint64) for name in (
         "submitted", "completed", "failed", "cancelled", "batches", "max_batch_seen",
-        "waiting", "running", "result_bytes", "workspace_share", "result_share", "overlapped")]
+        "waiting", "running", "result_bytes", "workspace_share", "result_share", "overlapped")] + \
+        [(name, C.c_double) for name in ("device_batch_ms", "device_busy_ms", "device_overlap_ms")]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+# nd_options.alloc / nd_options.free (include/nucleus.h)
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+
+
+def torch_allocator(device: int):
+    """(alloc, free) callbacks that take the library's device workspace from
+    PyTorch's caching allocator on ``device``, ordered on the stream the
+    library passes (so torch accounts for the memory and reuses it)."""
+    def alloc(nbytes, stream, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device, int(stream or 0))
+        except Exception:   # reported by the library as ND_E_OOM
+            return None
+
+    def free(ptr, nbytes, stream, user):
+        try:
+            torch.cuda.caching_allocator_delete(int(ptr))
+        except Exception:   # interpreter shutdown: torch is already gone
+            pass
+    return ALLOC_FN(alloc), FREE_FN(free)
 
 
 class NucleusError(RuntimeError):
@@ -232,6 +276,10 @@ def load_library(path: str = LIB_PATH):
     lib.nd_server_get_stats.restype = C.c_int
     lib.nd_server_last_error.argtypes = [vp]
     lib.nd_server_last_error.restype = C.c_char_p
+    lib.nd_cut.argtypes = [vp, C.c_uint32, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
+    lib.nd_cut.restype = C.c_int
+    lib.nd_get_cut.argtypes = [vp, vp, vp, vp, C.c_int]
+    lib.nd_get_cut.restype = C.c_int
     lib.nd_status_str.argtypes = [C.c_int]
     lib.nd_status_str.restype = C.c_char_p
     lib.nd_last_error.argtypes = [vp]
@@ -274,7 +322,9 @@ class Context:
     def __init__(self, device: int = 0, stream=None, validate: bool = True, mem_limit: int = 0,
                  peel_blocks: int = 0, work_chunk: int = 0, watchdog: int = 0,
                  use_torch_stream: bool = True, progress: bool = False,
-                 hierarchy: str = "auto"):
+                 hierarchy: str = "auto", allocator: str = "hip"):
+        """allocator: "hip" (the library's own hipMalloc) or "torch" (PyTorch's
+        caching allocator through the nd_options callbacks)."""
         self.lib = load_library()
         opt = Options()
         opt.device = device
@@ -288,6 +338,15 @@ class Context:
         opt.watchdog = watchdog
         opt.flags = (ND_FLAG_PROGRESS if progress else 0) | \
             {"auto": 0, "el": ND_FLAG_HIER_EL, "te": ND_FLAG_HIER_TE}[hierarchy]
+        self._alloc_cbs = None
+        if allocator == "torch":
+            if torch is None or not torch.cuda.is_available():
+                raise RuntimeError("allocator='torch' needs PyTorch with a GPU")
+            self._alloc_cbs = torch_allocator(device)
+            opt.alloc = C.cast(self._alloc_cbs[0], C.c_void_p)
+            opt.free = C.cast(self._alloc_cbs[1], C.c_void_p)
+        elif allocator != "hip":
+            raise ValueError(f"unknown allocator {allocator!r}")
         h = C.c_void_p()
         st = self.lib.nd_create(C.byref(h), C.byref(opt))
         if st != ND_OK:
@@ -394,6 +453,29 @@ class Context:
         self._check(self.lib.nd_get_tree(self.h, parent.ctypes.data if parent.size else None,
                                          level.ctypes.data if level.size else None, ND_MEM_HOST))
         return parent, level
+
+    def nd_cut(self, c: int) -> tuple[int, int]:
+        """Cut the last decomposition's tree at level c: (nuclei, vertices)."""
+        nn, nv = C.c_uint64(), C.c_uint64()
+        self._check(self.lib.nd_cut(self.h, c, C.byref(nn), C.byref(nv)))
+        return nn.value, nv.value
+
+    def cut(self, c: int) -> dict:
+        """The c-(r,s) nuclei: a structured array (node, min_leaf, n_rcliques,
+        n_vertices, n_edges, vert_off, level), their vertex lists and every
+        r-clique's nucleus (-1 = none), read back to the host."""
+        nn, nv = self.nd_cut(c)
+        n_r = self.nd_get_info()["n_r"]
+        nuc = np.zeros(nn, dtype=NUCLEUS_DTYPE)
+        verts = np.zeros(nv, dtype=np.uint32)
+        leaf = np.zeros(n_r, dtype=np.uint32)
+
+        def p(a):
+            return a.ctypes.data if a.size else None
+        self._check(self.lib.nd_get_cut(self.h, p(nuc), p(verts), p(leaf), ND_MEM_HOST))
+        leaf_i = leaf.astype(np.int64)
+        leaf_i[leaf == 0xFFFFFFFF] = -1
+        return {"nuclei": nuc, "verts": verts, "leaf_nucleus": leaf_i}
 
     def nd_batch_decompose(self, descs, results, where: int = ND_MEM_HOST):
         """descs / results: ctypes arrays of GraphDesc / GraphResult."""

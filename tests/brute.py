@@ -196,3 +196,37 @@ def brute_all(csr, r: int, s: int):
     parent, level = hierarchy_bfs(len(R), members, nd)
     return {"rcliques": R, "n_s": len(S), "count": deg, "coreness": nd,
             "parent": parent, "level": level}
+
+
+def nuclei_bfs(csr, r: int, s: int, c: int):
+    """The c-(r,s) nuclei by breadth-first search over s-clique adjacency
+    among the r-cliques of core >= c (core numbers by the fixed point above):
+    a list, ordered by smallest member, of (smallest member, smallest core
+    inside, r-clique count, sorted vertex tuple, edges of G among those
+    vertices)."""
+    adj = adjacency_sets(csr)
+    R, S, deg, members = s_clique_degrees(adj, r, s)
+    nd = coreness_fixpoint(len(R), members)
+    nbrs = [set() for _ in range(len(R))]
+    for ids in members:
+        for a, b in combinations(ids, 2):
+            nbrs[a].add(b)
+            nbrs[b].add(a)
+    out, seen = [], set()
+    for v in range(len(R)):
+        if nd[v] < c or v in seen:
+            continue
+        comp, stack = {v}, [v]
+        seen.add(v)
+        while stack:
+            x = stack.pop()
+            for y in nbrs[x]:
+                if nd[y] >= c and y not in seen:
+                    seen.add(y)
+                    comp.add(y)
+                    stack.append(y)
+        verts = sorted({u for i in comp for u in R[i]})
+        vs = set(verts)
+        edges = sum(1 for a in verts for b in adj[a] if b > a and b in vs)
+        out.append((min(comp), min(nd[i] for i in comp), len(comp), tuple(verts), edges))
+    return out

@@ -24,6 +24,9 @@ from paper_2306_08623_amd import inputs as I  # noqa: E402
 WORKLOADS = {
     "rmat18": (I.workload_rmat18, "R-MAT scale 18, edge factor 16, (a,b,c,d)=(.57,.19,.19,.05), seed 2"),
     "er2k": (I.workload_er2k, "G(2000, 0.01) + 20 planted cliques of size 5..30, seed 1"),
+    "chunglu4m": (I.workload_chung_lu_4m,
+                  "Chung-Lu n=4,000,000, exponent 2.1, max expected degree 20,000, ~40M edges, "
+                  "+ 1,000 communities of size 20..200 at density 0.6, seed 3"),
 }
 
 
@@ -45,6 +48,7 @@ def result_hashes(rcliques, counts, coreness, parent, level) -> dict:
 def main(name: str, r: int, s: int) -> None:
     gen, desc = WORKLOADS[name]
     g = gen()
+    print(f"{name}: n={g.n} m={g.m}, oracle ({r},{s}) started", flush=True)
     t0 = time.time()
     d = oracle.decompose(g, r, s)
     dt = time.time() - t0
@@ -53,6 +57,8 @@ def main(name: str, r: int, s: int) -> None:
         "workload": desc, "csr_sha256": g.sha256(), "n": g.n, "m": g.m, "r": r, "s": s,
         "n_r": d.n_r, "n_s": d.n_s, "k": d.k, "n_int": d.n_int,
         "oracle_seconds": round(dt, 1),
+        "oracle_phase_seconds": {"count": round(d.t_count, 1), "peel": round(d.t_peel, 1),
+                                 "tree": round(d.t_tree, 1)},
         "sha256": result_hashes(d.rcliques, d.count, d.coreness, d.parent, d.level),
     }
     path = os.path.join(HERE, f"{name}_{r}{s}.json")

@@ -14,17 +14,23 @@ sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
 
-def _source_hash() -> str:
+def _source_hash(kernel: str) -> str:
     src = os.path.join(ROOT, "paper_2306_08623_amd", "csrc")
-    return hashlib.sha256(open(os.path.join(src, "nd_peel.hip"), "rb").read() +
+    first = {"k_peel": "nd_peel.hip", "k_count_s4": "nd_count.hip"}[kernel]
+    return hashlib.sha256(open(os.path.join(src, first), "rb").read() +
                           open(os.path.join(src, "nd_internal.h"), "rb").read()).hexdigest()
 
 
-def _profile(path, digest: str) -> None:
-    with open(path, "w") as f:
-        f.write("traffic_bytes_per_launch k_peel<3,4> rmat18: 123456789\n")
-        f.write("traffic_bytes_per_launch k_count_s4<3> rmat18: 987654321\n")
-        f.write(f"peel source sha256 (nd_peel.hip + nd_internal.h) when measured: {digest}\n")
+def _profile(dirpath, workload: str, peel_digest: str, count_digest: str) -> None:
+    with open(os.path.join(dirpath, f"k_peel_{workload}_34.txt"), "w") as f:
+        f.write(f"traffic_bytes_per_launch k_peel<3,4> {workload} source {peel_digest}: 123456789\n")
+        f.write(f"traffic_bytes_per_launch k_count_s4<3,4> {workload} source {count_digest}: "
+                "987654321\n")
+
+
+def _use_dir(monkeypatch, d):
+    monkeypatch.setattr(bench, "profile_path",
+                        lambda k, w, r, s: os.path.join(str(d), f"{k}_{w}_{r}{s}.txt"))
 
 
 def test_more_than_one_gpu_is_refused():
@@ -36,21 +42,24 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_traffic_reported_for_matching_source(tmp_path, monkeypatch):
-    prof = tmp_path / "profile.txt"
-    _profile(prof, _source_hash())
-    monkeypatch.setattr(bench, "PROFILE", str(prof))
-    assert bench.measured_traffic("k_peel", "rmat18", 3, 4) == 123456789
-    assert bench.measured_traffic("k_count_s4", "rmat18", 3, 4) == 987654321
-    assert bench.measured_traffic("k_hier", "rmat18", 3, 4) is None
+    _profile(tmp_path, "chunglu4m", _source_hash("k_peel"), _source_hash("k_count_s4"))
+    _use_dir(monkeypatch, tmp_path)
+    assert bench.measured_traffic("k_peel", "chunglu4m", 3, 4) == 123456789
+    assert bench.measured_traffic("k_count_s4", "chunglu4m", 3, 4) == 987654321
+    assert bench.measured_traffic("k_hier", "chunglu4m", 3, 4) is None
 
 
 def test_traffic_withheld_for_changed_source_or_other_workload(tmp_path, monkeypatch):
-    prof = tmp_path / "profile.txt"
-    _profile(prof, "0" * 64)
-    monkeypatch.setattr(bench, "PROFILE", str(prof))
+    _use_dir(monkeypatch, tmp_path)
+    _profile(tmp_path, "chunglu4m", "0" * 64, "0" * 64)
+    assert bench.measured_traffic("k_peel", "chunglu4m", 3, 4) is None
+    assert bench.measured_traffic("k_count_s4", "chunglu4m", 3, 4) is None
+    _profile(tmp_path, "chunglu4m", _source_hash("k_peel"), _source_hash("k_count_s4"))
     assert bench.measured_traffic("k_peel", "rmat18", 3, 4) is None
-    _profile(prof, _source_hash())
-    assert bench.measured_traffic("k_peel", "er2k", 3, 4) is None
-    assert bench.measured_traffic("k_peel", "rmat18", 2, 3) is None
-    monkeypatch.setattr(bench, "PROFILE", str(tmp_path / "missing.txt"))
-    assert bench.measured_traffic("k_peel", "rmat18", 3, 4) is None
+    assert bench.measured_traffic("k_peel", "chunglu4m", 2, 3) is None
+
+
+def test_cpu_sample_is_the_benched_generator_scaled_down():
+    g, what = bench.cpu_sample("chunglu4m", 8)
+    assert g.n == 4_000_000 >> 8
+    assert "exponent 2.1" in what and "communities" in what

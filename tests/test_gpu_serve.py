@@ -154,3 +154,34 @@ def test_footprint_estimate_bounds_workspace():
         assert held <= ws + (4 << 20), (i, g.n, g.m, r, s, held, ws)
         n_int = res.level.size
         assert rb >= res.counts.size * (4 * r + 16) + n_int * 12, (i, rb)
+
+
+@pytest.mark.timeout(600)
+def test_serve_batches_overlap_on_device():
+    """Two pipelines with small batches: their batches run on the GPU at the
+    same time (device intervals from HIP events overlap), and every result
+    is still exactly the graph's solo result and the oracle's."""
+    from paper_2306_08623_amd import nucleus
+    reqs = [I.serve_graph(100 + i, m_hi=150_000) for i in range(32)]
+    with nucleus.Context(device=0) as ctx:
+        solo = [ctx.decompose(g, r, s) for g, r, s in reqs]
+    _say(f"[serve] {len(reqs)} requests, 2 pipelines, batches of at most 4")
+    with nucleus.Server(device=0, workers=2, max_batch=4) as srv:
+        tickets = [srv.submit(g, r, s) for g, r, s in reqs]
+        mix = []
+        for t, (g, r, s) in zip(tickets, reqs):
+            res = srv.get(t, r)
+            assert res.info["status"] == nucleus.ND_OK
+            srv.release(t)
+            mix.append(res)
+        st = srv.stats()
+    _say(f"[serve] device batch {st['device_batch_ms']:.1f} ms, busy {st['device_busy_ms']:.1f} "
+         f"ms, overlapped {st['device_overlap_ms']:.1f} ms over {st['batches']} batches")
+    assert st["completed"] == len(reqs) and st["batches"] >= 8
+    assert st["device_overlap_ms"] > 0.0
+    assert st["device_batch_ms"] >= st["device_busy_ms"] >= st["device_overlap_ms"]
+    for i, (g, r, s) in enumerate(reqs):
+        _same(mix[i], solo[i], ("overlapped mix vs solo", i))
+    for i in range(0, len(reqs), 4):
+        g, r, s = reqs[i]
+        _vs_oracle(mix[i], g, r, s, ("oracle", i, g.n, g.m, r, s))
