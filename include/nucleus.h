@@ -145,6 +145,9 @@ typedef struct nd_info {
                              union of two roots, and the L updates of
                              Algorithm 5 (EL) / of the hierarchy pass (TE)    */
   uint64_t device_peak;   /* largest workspace held during this run (bytes)   */
+  double approx_delta;    /* delta of an approximate run (0: exact)           */
+  uint32_t round_cap;     /* approximate run: rounds a bucket is processed at
+                             most (Algorithm 2)                               */
 } nd_info;
 
 /* Create a context on opt->device (opt may be NULL: device 0, null stream,
@@ -166,6 +169,25 @@ nd_status nd_load_csr(nd_ctx *ctx, uint32_t n, uint64_t nnz, const uint64_t *row
  * (2,3) (k-truss), (1,3), (1,4), (2,4), (3,4). Pairs with s > 4 return
  * ND_E_UNSUPPORTED; r < 1 or r >= s returns ND_E_INVALID_ARG. */
 nd_status nd_set_rs(nd_ctx *ctx, uint32_t r, uint32_t s);
+
+/* Approximate decomposition (Section 6, Algorithm 2): with delta > 0 the
+ * next nd_decompose calls peel by geometric buckets instead of exact levels;
+ * delta = 0 restores exact peeling (the default). Bucket i holds current
+ * s-clique degrees up to thr[i] = floor((C(s,r) + delta) (1 + delta)^(i+1))
+ * (double precision, the power by repeated multiplication). A round at
+ * bucket i peels every remaining r-clique of degree <= thr[i] and gives it
+ * thr[i] as its (approximate) core number; the s-cliques it removes lower
+ * the degrees of the others as in exact peeling. A bucket is left when it
+ * is empty or after T = floor(ln n_r / ln(1 + delta / C(s,r))) + 1 rounds,
+ * its remaining r-cliques carried into the next. r-cliques in no s-clique
+ * get 0. Theorem 6.1: core <= approx <= (C(s,r) + delta)(1 + delta) core.
+ * The hierarchy and every getter work on these values exactly as on exact
+ * core numbers. Batches (nd_batch_decompose) always peel exactly: the
+ * rounds of a union are not those of its graphs; a context in approximate
+ * mode refuses them (ND_E_UNSUPPORTED). delta must be finite and in
+ * [0, 64], else ND_E_INVALID_ARG. Bucket ends that would pass 2^32 - 1
+ * stop the run with ND_E_UNSUPPORTED. */
+nd_status nd_set_approx(nd_ctx *ctx, double delta);
 
 /* Run the whole pipeline on the context's stream: orientation, r-clique
  * tables, s-clique counting, peel rounds with linking, tree construction and

@@ -89,6 +89,9 @@ def _load():
         lib.ndo_open.argtypes = [C.c_uint32, u64p, u32p, C.c_uint32, C.c_uint32,
                                  C.POINTER(C.c_void_p)]
         lib.ndo_open.restype = C.c_int
+        lib.ndo_approx_decompose.argtypes = [C.c_uint32, u64p, u32p, C.c_uint32, C.c_uint32,
+                                             C.c_double, C.POINTER(_Result)]
+        lib.ndo_approx_decompose.restype = C.c_int
         lib.ndo_nuclei.argtypes = [C.c_uint32, u64p, u32p, C.c_uint32, C.c_uint32, u64p,
                                    C.c_uint64, C.POINTER(_Cut)]
         lib.ndo_nuclei.restype = C.c_int
@@ -153,12 +156,12 @@ def validate(csr) -> int:
                                 col.ctypes.data_as(C.POINTER(C.c_uint32)))
 
 
-def _run(fn_name: str, csr, r: int, s: int, full: bool) -> Decomposition:
+def _run(fn_name: str, csr, r: int, s: int, full: bool, *extra) -> Decomposition:
     lib = _load()
     rp, col = _csr_args(csr)
     res = _Result()
     st = getattr(lib, fn_name)(csr.n, rp.ctypes.data_as(C.POINTER(C.c_uint64)),
-                               col.ctypes.data_as(C.POINTER(C.c_uint32)), r, s,
+                               col.ctypes.data_as(C.POINTER(C.c_uint32)), r, s, *extra,
                                C.byref(res))
     if st != NDO_OK:
         raise OracleError(st)
@@ -229,6 +232,12 @@ class Graph:
 def decompose(csr, r: int, s: int) -> Decomposition:
     """Full oracle: r-cliques, counts, coreness, canonical tree."""
     return _run("ndo_decompose", csr, r, s, True)
+
+
+def approx_decompose(csr, r: int, s: int, delta: float) -> Decomposition:
+    """Approximate core numbers (Algorithm 2, round-synchronous, geometric
+    buckets of parameter delta) and the canonical tree of those values."""
+    return _run("ndo_approx_decompose", csr, r, s, True, C.c_double(delta))
 
 
 def count(csr, r: int, s: int) -> Decomposition:

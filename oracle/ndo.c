@@ -21,6 +21,7 @@
 #define _POSIX_C_SOURCE 199309L
 #include "ndo.h"
 
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 #include <time.h>
@@ -517,6 +518,129 @@ static int do_count(const graph *g, uint32_t r, uint32_t s, ndo_result *out, rta
   return NDO_OK;
 }
 
+/* O4 + O5 for the core numbers in out->coreness, peeled in the order
+ * out->peel_order (core numbers non-decreasing along it): the hierarchy of
+ * Section 5 / 7.4 by one union-find over descending levels, then canonical
+ * numbering. Takes ownership of `gone` (n_r bytes, reused as the active
+ * flags). X is a scan of the graph whose fn is emit_link. */
+static int build_tree(const rtable *T, uint32_t r, uint32_t s, ndo_result *out, sscan *X,
+                      uint8_t *gone) {
+  const uint64_t nr = T->n_r;
+  const uint64_t nr1 = nr ? nr : 1;
+  uint32_t tup[MAXS];
+  /* O4: hierarchy, levels from k down to 1 (reverse peel order is sorted by
+   * non-increasing core number). */
+  uint64_t *uf = (uint64_t *)malloc(nr1 * sizeof(uint64_t));
+  uint64_t *stamp = (uint64_t *)malloc(nr1 * sizeof(uint64_t));
+  uint64_t *top = (uint64_t *)malloc(nr1 * sizeof(uint64_t));
+  uint64_t *par = (uint64_t *)malloc(2 * nr1 * sizeof(uint64_t));
+  uint64_t *minleaf = (uint64_t *)malloc(2 * nr1 * sizeof(uint64_t));
+  uint64_t *nlevel = (uint64_t *)malloc(nr1 * sizeof(uint64_t));
+  uint8_t *active = gone;     /* reused: cleared below */
+  vec64 pieces;
+  memset(&pieces, 0, sizeof(pieces));
+  if (!uf || !stamp || !top || !par || !minleaf || !nlevel) {
+    free(uf); free(stamp); free(top); free(par); free(minleaf); free(nlevel); free(active);
+    return NDO_E_OOM;
+  }
+  memset(active, 0, nr1);
+  for (uint64_t i = 0; i < nr; i++) { uf[i] = i; stamp[i] = NONE; top[i] = i; }
+  for (uint64_t i = 0; i < 2 * nr1; i++) { par[i] = NONE; minleaf[i] = i; }
+  uint64_t nint = 0;
+  linker K;
+  memset(&K, 0, sizeof(K));
+  K.T = T; K.s = s; K.active = active; K.uf = uf; K.stamp = stamp; K.pieces = &pieces;
+  make_subsets(&K.sb, r, s);
+  X->ctx = &K;
+  uint64_t hi = nr;   /* process peel_order[lo..hi) in reverse */
+  int oom = 0;
+  while (hi > 0) {
+    uint64_t c = out->coreness[out->peel_order[hi - 1]];
+    uint64_t lo = hi;
+    while (lo > 0 && out->coreness[out->peel_order[lo - 1]] == c) lo--;
+    if (c == 0) break;   /* core-0 r-cliques lie in no s-clique: root leaves */
+    for (uint64_t i = lo; i < hi; i++) active[out->peel_order[i]] = 1;
+    /* pieces: the level-c r-cliques themselves and the current components
+     * (of levels > c) they touch */
+    pieces.n = 0;
+    K.level = c;
+    K.do_union = 0;
+    for (uint64_t i = lo; i < hi; i++) {
+      uint64_t R = out->peel_order[i];
+      if (stamp[R] != c) { stamp[R] = c; v64_push(&pieces, R); }
+      K.self = R;
+      memcpy(tup, T->t + R * r, r * sizeof(uint32_t));
+      for_each_sclique(X, tup);
+    }
+    K.do_union = 1;
+    for (uint64_t i = lo; i < hi; i++) {
+      uint64_t R = out->peel_order[i];
+      K.self = R;
+      memcpy(tup, T->t + R * r, r * sizeof(uint32_t));
+      for_each_sclique(X, tup);
+    }
+    if (pieces.oom) { oom = 1; break; }
+    /* group the pieces by their new root; groups of >= 2 pieces are the new
+     * components of size >= 2, i.e. the level-c tree nodes */
+    kv *grp = (kv *)malloc((pieces.n ? pieces.n : 1) * sizeof(kv));
+    if (!grp) { oom = 1; break; }
+    for (uint64_t i = 0; i < pieces.n; i++) {
+      grp[i].key = uf_find(uf, pieces.a[i]);
+      grp[i].val = pieces.a[i];
+    }
+    qsort(grp, pieces.n, sizeof(kv), kv_cmp);
+    for (uint64_t i = 0; i < pieces.n;) {
+      uint64_t j = i;
+      while (j < pieces.n && grp[j].key == grp[i].key) j++;
+      if (j - i >= 2) {
+        uint64_t node = nr + nint;
+        nlevel[nint] = c;
+        nint++;
+        uint64_t ml = NONE;
+        for (uint64_t t = i; t < j; t++) {
+          uint64_t child = top[grp[t].val];
+          par[child] = node;
+          if (minleaf[child] < ml) ml = minleaf[child];
+        }
+        minleaf[node] = ml;
+        top[grp[i].key] = node;
+      }
+      i = j;
+    }
+    free(grp);
+    hi = lo;
+  }
+  free(pieces.a); free(uf); free(stamp); free(top); free(active);
+  if (oom) { free(par); free(minleaf); free(nlevel); return NDO_E_OOM; }
+
+  /* O5: canonical numbering by (level, min leaf) */
+  nodekey *keys = (nodekey *)malloc((nint ? nint : 1) * sizeof(nodekey));
+  uint64_t *canon = (uint64_t *)malloc((nint ? nint : 1) * sizeof(uint64_t));
+  out->parent = (uint64_t *)malloc((nr + nint ? nr + nint : 1) * sizeof(uint64_t));
+  out->level = (uint64_t *)malloc((nint ? nint : 1) * sizeof(uint64_t));
+  if (!keys || !canon || !out->parent || !out->level) {
+    free(keys); free(canon); free(par); free(minleaf); free(nlevel);
+    return NDO_E_OOM;
+  }
+  for (uint64_t i = 0; i < nint; i++) {
+    keys[i].level = nlevel[i];
+    keys[i].minleaf = minleaf[nr + i];
+    keys[i].node = i;
+  }
+  qsort(keys, nint, sizeof(nodekey), nodekey_cmp);
+  for (uint64_t i = 0; i < nint; i++) canon[keys[i].node] = nr + i;
+  for (uint64_t x = 0; x < nr; x++)
+    out->parent[x] = par[x] == NONE ? NONE : canon[par[x] - nr];
+  for (uint64_t i = 0; i < nint; i++) {
+    uint64_t p = par[nr + i];
+    out->parent[canon[i]] = p == NONE ? NONE : canon[p - nr];
+    out->level[canon[i] - nr] = nlevel[i];
+  }
+  out->n_int = nint;
+  free(keys); free(canon); free(par); free(minleaf); free(nlevel);
+  return NDO_OK;
+}
+
 int ndo_count(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
               uint32_t r, uint32_t s, ndo_result *out) {
   if (!out) return NDO_E_INVALID_ARG;
@@ -605,119 +729,158 @@ int ndo_decompose(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
   double t2 = now_s();
   out->t_peel = t2 - t1;
 
-  /* O4: hierarchy, levels from k down to 1 (reverse peel order is sorted by
-   * non-increasing core number). */
-  uint64_t *uf = (uint64_t *)malloc(nr1 * sizeof(uint64_t));
-  uint64_t *stamp = (uint64_t *)malloc(nr1 * sizeof(uint64_t));
-  uint64_t *top = (uint64_t *)malloc(nr1 * sizeof(uint64_t));
-  uint64_t *par = (uint64_t *)malloc(2 * nr1 * sizeof(uint64_t));
-  uint64_t *minleaf = (uint64_t *)malloc(2 * nr1 * sizeof(uint64_t));
-  uint64_t *nlevel = (uint64_t *)malloc(nr1 * sizeof(uint64_t));
-  uint8_t *active = P.gone;   /* reuse: cleared below */
-  vec64 pieces;
-  memset(&pieces, 0, sizeof(pieces));
-  if (!uf || !stamp || !top || !par || !minleaf || !nlevel) {
-    free(uf); free(stamp); free(top); free(par); free(minleaf); free(nlevel); free(active);
-    sscan_free(&X); free(T.first); ndo_free(out);
-    return NDO_E_OOM;
-  }
-  memset(active, 0, nr1);
-  for (uint64_t i = 0; i < nr; i++) { uf[i] = i; stamp[i] = NONE; top[i] = i; }
-  for (uint64_t i = 0; i < 2 * nr1; i++) { par[i] = NONE; minleaf[i] = i; }
-  uint64_t nint = 0;
-  linker K;
-  memset(&K, 0, sizeof(K));
-  K.T = &T; K.s = s; K.active = active; K.uf = uf; K.stamp = stamp; K.pieces = &pieces;
-  make_subsets(&K.sb, r, s);
+  /* O4 + O5: the hierarchy of these core numbers */
   X.fn = emit_link;
-  X.ctx = &K;
-  uint64_t hi = nr;   /* process peel_order[lo..hi) in reverse */
-  int oom = 0;
-  while (hi > 0) {
-    uint64_t c = out->coreness[out->peel_order[hi - 1]];
-    uint64_t lo = hi;
-    while (lo > 0 && out->coreness[out->peel_order[lo - 1]] == c) lo--;
-    if (c == 0) break;   /* core-0 r-cliques lie in no s-clique: root leaves */
-    for (uint64_t i = lo; i < hi; i++) active[out->peel_order[i]] = 1;
-    /* pieces: the level-c r-cliques themselves and the current components
-     * (of levels > c) they touch */
-    pieces.n = 0;
-    K.level = c;
-    K.do_union = 0;
-    for (uint64_t i = lo; i < hi; i++) {
-      uint64_t R = out->peel_order[i];
-      if (stamp[R] != c) { stamp[R] = c; v64_push(&pieces, R); }
-      K.self = R;
-      memcpy(tup, T.t + R * r, r * sizeof(uint32_t));
-      for_each_sclique(&X, tup);
-    }
-    K.do_union = 1;
-    for (uint64_t i = lo; i < hi; i++) {
-      uint64_t R = out->peel_order[i];
-      K.self = R;
-      memcpy(tup, T.t + R * r, r * sizeof(uint32_t));
-      for_each_sclique(&X, tup);
-    }
-    if (pieces.oom) { oom = 1; break; }
-    /* group the pieces by their new root; groups of >= 2 pieces are the new
-     * components of size >= 2, i.e. the level-c tree nodes */
-    kv *grp = (kv *)malloc((pieces.n ? pieces.n : 1) * sizeof(kv));
-    if (!grp) { oom = 1; break; }
-    for (uint64_t i = 0; i < pieces.n; i++) {
-      grp[i].key = uf_find(uf, pieces.a[i]);
-      grp[i].val = pieces.a[i];
-    }
-    qsort(grp, pieces.n, sizeof(kv), kv_cmp);
-    for (uint64_t i = 0; i < pieces.n;) {
-      uint64_t j = i;
-      while (j < pieces.n && grp[j].key == grp[i].key) j++;
-      if (j - i >= 2) {
-        uint64_t node = nr + nint;
-        nlevel[nint] = c;
-        nint++;
-        uint64_t ml = NONE;
-        for (uint64_t t = i; t < j; t++) {
-          uint64_t child = top[grp[t].val];
-          par[child] = node;
-          if (minleaf[child] < ml) ml = minleaf[child];
-        }
-        minleaf[node] = ml;
-        top[grp[i].key] = node;
-      }
-      i = j;
-    }
-    free(grp);
-    hi = lo;
-  }
+  st = build_tree(&T, r, s, out, &X, P.gone);
   sscan_free(&X);
-  free(pieces.a); free(uf); free(stamp); free(top); free(active);
-  if (oom) { free(par); free(minleaf); free(nlevel); free(T.first); ndo_free(out); return NDO_E_OOM; }
+  if (st != NDO_OK) { free(T.first); ndo_free(out); return st; }
+  out->t_tree = now_s() - t2;
+  free(T.first);
+  return NDO_OK;
+}
 
-  /* O5: canonical numbering by (level, min leaf) */
-  nodekey *keys = (nodekey *)malloc((nint ? nint : 1) * sizeof(nodekey));
-  uint64_t *canon = (uint64_t *)malloc((nint ? nint : 1) * sizeof(uint64_t));
-  out->parent = (uint64_t *)malloc((nr + nint ? nr + nint : 1) * sizeof(uint64_t));
-  out->level = (uint64_t *)malloc((nint ? nint : 1) * sizeof(uint64_t));
-  if (!keys || !canon || !out->parent || !out->level) {
-    free(keys); free(canon); free(par); free(minleaf); free(nlevel); free(T.first); ndo_free(out);
+/* ---- approximate decomposition (Section 6, Algorithm 2) ------------------ */
+
+/* Upper ends of the geometric buckets: thr[i] = floor((C + delta) *
+ * (1 + delta)^(i+1)), the product formed by repeated multiplication in
+ * double precision; the list ends with the first value of 2^32 or more
+ * (stored as 2^32). Returns the number of entries (at most cap). */
+static uint32_t approx_thresholds(uint64_t C, double delta, uint64_t *thr, uint32_t cap) {
+  double t = (double)C + delta;
+  uint32_t nb = 0;
+  while (nb < cap) {
+    t *= 1.0 + delta;
+    if (t >= 4294967296.0) { thr[nb++] = 4294967296ull; break; }
+    thr[nb++] = (uint64_t)t;   /* floor of a positive value */
+  }
+  return nb;
+}
+
+/* Rounds a bucket is processed at most: the smallest T with
+ * n_r * (C / (C + delta))^T < 1 (Lemma 2: each round leaves at most a
+ * C / (C + delta) share of the r-cliques of core <= l outside the bucket). */
+static uint64_t approx_round_cap(uint64_t C, double delta, uint64_t nr) {
+  if (nr <= 1) return 1;
+  return (uint64_t)(log((double)nr) / log(1.0 + delta / (double)C)) + 1;
+}
+
+typedef struct {
+  const rtable *T;
+  uint32_t s;
+  uint64_t self;
+  uint64_t t;           /* current round */
+  subsets sb;
+  const uint64_t *round;  /* peel round, NONE while unpeeled */
+  uint64_t *deg;
+} approx_peeler;
+
+/* s-clique S of a peeled r-clique R in round t: if no member of S was
+ * peeled in an earlier round (S still exists) and R is the smallest member
+ * of S peeled in round t, S is removed once: every member not peeled yet
+ * loses one s-clique */
+static void emit_approx(const uint32_t *S, void *ctx) {
+  approx_peeler *P = (approx_peeler *)ctx;
+  uint32_t sub[MAXS];
+  uint64_t ids[128];
+  uint32_t no = 0;
+  for (uint32_t i = 0; i < P->sb.nm; i++) {
+    subset_tuple(S, P->s, P->sb.mask[i], sub);
+    uint64_t id = rlookup(P->T, sub);
+    if (id == P->self) continue;
+    uint64_t rd = P->round[id];
+    if (rd != NONE && rd < P->t) return;            /* S was destroyed earlier */
+    if (rd == P->t && id < P->self) return;        /* a smaller member removes S */
+    ids[no++] = id;
+  }
+  for (uint32_t i = 0; i < no; i++)
+    if (P->round[ids[i]] == NONE) P->deg[ids[i]]--;
+}
+
+int ndo_approx_decompose(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, uint32_t r,
+                         uint32_t s, double delta, ndo_result *out) {
+  if (!out) return NDO_E_INVALID_ARG;
+  memset(out, 0, sizeof(*out));
+  if (r < 1 || s <= r || s > MAXS || !(delta > 0.0)) return NDO_E_INVALID_ARG;
+  graph g;
+  int st = build_graph(&g, n, row_ptr, col);
+  if (st != NDO_OK) return st;
+  out->n = n; out->r = r; out->s = s;
+  double t0 = now_s();
+  rtable T;
+  memset(&T, 0, sizeof(T));
+  st = do_count(&g, r, s, out, &T);
+  if (st != NDO_OK) { free(T.first); ndo_free(out); return st; }
+  const uint64_t nr = T.n_r, nr1 = nr ? nr : 1;
+  double t1 = now_s();
+  out->t_count = t1 - t0;
+
+  subsets sb;
+  make_subsets(&sb, r, s);
+  const uint64_t C = sb.nm;   /* C(s, r) */
+  uint64_t thr[4096];
+  const uint32_t nb = approx_thresholds(C, delta, thr, 4096);
+  const uint64_t cap = approx_round_cap(C, delta, nr);
+  out->coreness = (uint64_t *)calloc(nr1, sizeof(uint64_t));
+  out->peel_order = (uint64_t *)calloc(nr1, sizeof(uint64_t));
+  uint64_t *deg = (uint64_t *)malloc(nr1 * sizeof(uint64_t));
+  uint64_t *round = (uint64_t *)malloc(nr1 * sizeof(uint64_t));
+  uint64_t *A = (uint64_t *)malloc(nr1 * sizeof(uint64_t));
+  uint8_t *gone = (uint8_t *)calloc(nr1, 1);
+  approx_peeler P;
+  memset(&P, 0, sizeof(P));
+  P.T = &T; P.s = s; P.sb = sb; P.round = round; P.deg = deg;
+  sscan X;
+  int sst = sscan_init(&X, &g, r, s, emit_approx, &P);
+  if (!out->coreness || !out->peel_order || !deg || !round || !A || !gone || sst != NDO_OK) {
+    free(deg); free(round); free(A); free(gone); sscan_free(&X); free(T.first); ndo_free(out);
     return NDO_E_OOM;
   }
-  for (uint64_t i = 0; i < nint; i++) {
-    keys[i].level = nlevel[i];
-    keys[i].minleaf = minleaf[nr + i];
-    keys[i].node = i;
+  for (uint64_t i = 0; i < nr; i++) { deg[i] = out->count[i]; round[i] = NONE; }
+  /* r-cliques in no s-clique: core 0, peeled first */
+  uint64_t done = 0, t = 0;
+  for (uint64_t R = 0; R < nr; R++)
+    if (deg[R] == 0) { round[R] = 0; out->coreness[R] = 0; out->peel_order[done++] = R; }
+  if (done) t = 1;
+  /* buckets in order; a bucket is left when it is empty or after `cap`
+   * rounds, its remaining r-cliques carried into the next */
+  uint32_t b = 0;
+  uint64_t rounds_here = 0, kmax = 0;
+  int overflow = 0;
+  while (done < nr) {
+    if (b >= nb || thr[b] >= 4294967296ull) { overflow = 1; break; }
+    const uint64_t lvl = thr[b];
+    uint64_t na = 0;
+    for (uint64_t R = 0; R < nr; R++)
+      if (round[R] == NONE && deg[R] <= lvl) A[na++] = R;
+    if (na == 0) { b++; rounds_here = 0; continue; }
+    for (uint64_t i = 0; i < na; i++) {
+      round[A[i]] = t;
+      out->coreness[A[i]] = lvl;
+      out->peel_order[done++] = A[i];
+    }
+    kmax = lvl;
+    uint32_t tup[MAXS];
+    P.t = t;
+    for (uint64_t i = 0; i < na; i++) {
+      P.self = A[i];
+      memcpy(tup, T.t + A[i] * r, r * sizeof(uint32_t));
+      for_each_sclique(&X, tup);
+    }
+    t++;
+    if (++rounds_here >= cap) { b++; rounds_here = 0; }
   }
-  qsort(keys, nint, sizeof(nodekey), nodekey_cmp);
-  for (uint64_t i = 0; i < nint; i++) canon[keys[i].node] = nr + i;
-  for (uint64_t x = 0; x < nr; x++)
-    out->parent[x] = par[x] == NONE ? NONE : canon[par[x] - nr];
-  for (uint64_t i = 0; i < nint; i++) {
-    uint64_t p = par[nr + i];
-    out->parent[canon[i]] = p == NONE ? NONE : canon[p - nr];
-    out->level[canon[i] - nr] = nlevel[i];
+  free(deg); free(round); free(A);
+  if (overflow) {
+    free(gone); sscan_free(&X); free(T.first); ndo_free(out);
+    return NDO_E_INVALID_ARG;
   }
-  out->n_int = nint;
-  free(keys); free(canon); free(par); free(minleaf); free(nlevel);
+  out->k = kmax;
+  double t2 = now_s();
+  out->t_peel = t2 - t1;
+  X.fn = emit_link;
+  st = build_tree(&T, r, s, out, &X, gone);
+  sscan_free(&X);
+  if (st != NDO_OK) { free(T.first); ndo_free(out); return st; }
   out->t_tree = now_s() - t2;
   free(T.first);
   return NDO_OK;

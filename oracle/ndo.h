@@ -82,6 +82,21 @@ int ndo_count(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
 
 void ndo_free(ndo_result *res);
 
+/* Approximate decomposition and its hierarchy (Section 6, Algorithm 2;
+ * hierarchy as for exact core numbers). Buckets of s-clique degree with
+ * upper ends thr[i] = floor((C(s,r) + delta) * (1 + delta)^(i+1)) (double
+ * precision, the power by repeated multiplication); rounds are synchronous:
+ * a round at bucket i peels every unpeeled r-clique of current degree
+ * <= thr[i], assigns it thr[i], and removes each s-clique that still exists
+ * once (from its smallest member peeled in that round). A bucket is left
+ * when it is empty or after T = floor(ln n_r / ln(1 + delta / C(s,r))) + 1
+ * rounds. r-cliques in no s-clique get 0. The approximation satisfies
+ * core <= approx <= (C(s,r) + delta)(1 + delta) core (Theorem 6.1).
+ * peel_order lists r-cliques in round order; k is the largest value
+ * assigned. NDO_E_INVALID_ARG also when a bucket end would pass 2^32 - 1. */
+int ndo_approx_decompose(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, uint32_t r,
+                         uint32_t s, double delta, ndo_result *out);
+
 /* The c-(r,s) nuclei from the definition (Section 8, on the usefulness of
  * the hierarchy: without a hierarchy, the nuclei of level c are the
  * connected components of the r-cliques of core number >= c under s-clique

@@ -338,6 +338,14 @@ nd_status nd_load_csr(nd_ctx *c, uint32_t n, uint64_t nnz, const uint64_t *row_p
   return ND_OK;
 }
 
+nd_status nd_set_approx(nd_ctx *c, double delta) {
+  if (!c) return ND_E_INVALID_ARG;
+  if (!(delta >= 0.0 && delta <= 64.0))
+    return nd_fail(c, ND_E_INVALID_ARG, "delta must be in [0, 64]");
+  c->approx_delta = delta;   // applies to the next decomposition; results stay readable
+  return ND_OK;
+}
+
 nd_status nd_set_rs(nd_ctx *c, uint32_t r, uint32_t s) {
   if (!c) return ND_E_INVALID_ARG;
   if (r < 1 || s <= r) return nd_fail(c, ND_E_INVALID_ARG, "need 1 <= r < s");
@@ -424,6 +432,8 @@ nd_status nd_run_pipeline(nd_ctx *c) {
   I.orient_rounds = hs.orient_round;
   I.device_bytes = c->bytes_held;
   I.device_peak = c->bytes_peak;
+  I.approx_delta = c->approx_delta;
+  if (c->approx_delta <= 0) I.round_cap = 0;
   I.cas_retries = hs.cas_retries;
   I.cascades = (!I.hier_te && hs.links > hs.link_calls) ? hs.links - hs.link_calls : 0;
   if (c->events_ok) {

@@ -555,6 +555,10 @@ nd_status nd_batch_decompose(nd_ctx *c, uint32_t G, const nd_graph_desc *graphs,
                              nd_graph_result *results) {
   if (!c) return ND_E_INVALID_ARG;
   c->last_error.clear();
+  if (c->approx_delta > 0)
+    return nd_fail(c, ND_E_UNSUPPORTED,
+                   "batches peel exactly: the approximate rounds of a union are not those of "
+                   "its graphs (nd_set_approx(ctx, 0) first)");
   nd_batch_release(c);
   c->have_graph = false;
   c->decomposed = false;

@@ -328,6 +328,7 @@ struct nd_ctx {
   uint32_t n = 0;
   uint64_t nnz = 0, m = 0;
   uint32_t r = 0, s = 0;
+  double approx_delta = 0;   // > 0: approximate decomposition (Algorithm 2)
   bool decomposed = false;
   bool info_valid = false;   // info holds the last decomposition or batch
 
@@ -378,6 +379,7 @@ enum BufId : int {
   // hierarchy cut (nd_cut.hip)
   B_CUT_TOP, B_CUT_POS, B_CUT_LEAF, B_CUT_NUC, B_CUT_RCL, B_CUT_K0, B_CUT_K1, B_CUT_V0,
   B_CUT_V1, B_CUT_FLAG, B_CUT_POS2, B_CUT_VERTS, B_CUT_VNUC, B_CUT_CNT,
+  B_THR,   // approximate decomposition: bucket ends
   B_COUNT
 };
 

@@ -32,6 +32,7 @@
 #include "nd_internal.h"
 
 #include <algorithm>
+#include <cmath>
 #include <cstddef>
 #include <cstring>
 
@@ -67,6 +68,12 @@ struct PeelArgs {
   uint32_t nblocks;
   uint32_t max_rounds;
   uint32_t *progress;   // host-visible [round, level, frontier], or null
+  // approximate decomposition (Algorithm 2): the upper ends of the
+  // geometric buckets (n_thr of them; 0 = exact peeling) and the most rounds
+  // a bucket is processed before the next bucket takes over
+  const uint32_t *thr;
+  uint32_t n_thr;
+  uint32_t round_cap;
 };
 
 // ---------------------------------------------------------------------------
@@ -745,6 +752,9 @@ __global__ void __launch_bounds__(kPeelBlock, 5) k_peel(PeelArgs a) {
   uint32_t t = 0;
   uint32_t nscan = 0;   // bucket scans done
   uint32_t fprev = 0;   // frontier size of the previous round
+  uint32_t bi = 0;      // approximate mode: current bucket
+  uint32_t rib = 0;     // approximate mode: rounds in the current bucket
+  const bool approx = a.n_thr != 0;
   bool done = false;
 
   while (!done) {
@@ -755,8 +765,14 @@ __global__ void __launch_bounds__(kPeelBlock, 5) k_peel(PeelArgs a) {
     uint32_t *F = (t & 1) ? a.F1 : a.F0;
     uint32_t *Fn = (t & 1) ? a.F0 : a.F1;
     uint32_t f = ld_acq32(&sc->fsize[t & 1]);
+    // approximate mode: a bucket that has had its rounds passes its
+    // remaining r-cliques to the next bucket; the scan rebuilds the frontier
+    // from the remaining list, so the collected one is dropped (every
+    // workgroup takes this branch: rib is the same everywhere)
+    const bool forced = approx && rib >= a.round_cap;
+    if (forced && gtid == 0) sc->fsize[t & 1] = 0;
 
-    if (f == 0) {
+    if (f == 0 || forced) {
       // ---- bucket scan: new level = minimum count of the remaining r-cliques.
       // Every workgroup owns one segment of the id range and keeps the list
       // of its still-present r-cliques compacted in place (order preserved),
@@ -826,9 +842,24 @@ __global__ void __launch_bounds__(kPeelBlock, 5) k_peel(PeelArgs a) {
         sc->n_alive[qp] = 0;         // becomes the total of the next scan
         sc->kmin[qp ^ 1] = ND_NONE;  // minimum of the next scan
       }
-      // the new frontier: entries at the new level (none in a segment whose
-      // minimum is above it)
-      if (s_bmin == kq) {
+      // the new level: exact, the minimum; approximate, the end of the first
+      // bucket (from the current one, or the next when forced) that reaches
+      // the minimum, 0 for r-cliques in no s-clique
+      uint32_t lvl = kq;
+      if (approx && kq != 0) {
+        uint32_t b = bi + (forced ? 1u : 0u);
+        while (b < a.n_thr && a.thr[b] < kq) b++;
+        if (b >= a.n_thr) {   // a bucket end beyond 32 bits
+          if (gtid == 0) atomicOr(&sc->status, ND_DERR_OVERFLOW);
+          break;
+        }
+        bi = b;
+        lvl = a.thr[b];
+      }
+      rib = 0;
+      // the new frontier: remaining entries at or below the new level (none
+      // in a segment whose minimum is above it)
+      if (s_bmin <= lvl) {
         for (uint32_t base = 0; base < nkeep; base += kPeelBlock * kScanU) {
           const uint32_t i0 = base + threadIdx.x * kScanU;
           uint32_t id[kScanU];
@@ -838,7 +869,7 @@ __global__ void __launch_bounds__(kPeelBlock, 5) k_peel(PeelArgs a) {
           uint32_t nt = 0;
 #pragma unroll
           for (uint32_t u = 0; u < kScanU; u++) {
-            take[u] = i0 + u < nkeep && a.cnt[id[u]] == kq;
+            take[u] = i0 + u < nkeep && a.cnt[id[u]] <= lvl;
             nt += take[u];
           }
           const uint32_t incl = wave_incl_scan(nt);
@@ -853,7 +884,7 @@ __global__ void __launch_bounds__(kPeelBlock, 5) k_peel(PeelArgs a) {
       }
       scans++;
       nscan++;
-      k = kq;
+      k = lvl;
       if (!grid_barrier(sc->bar, nb, &sc->status)) break;
       f = ld_acq32(&sc->fsize[t & 1]);
     }
@@ -1066,6 +1097,7 @@ __global__ void __launch_bounds__(kPeelBlock, 5) k_peel(PeelArgs a) {
     }
     if (!ok) break;
     t++;
+    rib++;
   }
 
   // statistics
@@ -1418,6 +1450,37 @@ nd_status nd_stage_peel(nd_ctx *c, const GraphView &g) {
     pa.gcache_mask = ge - 1;
     if ((st = nd_hip(c, hipMemsetAsync(pa.gcache, 0xFF, ge * 8, c->stream), "gcache")) != ND_OK)
       return st;
+  }
+  if (c->approx_delta > 0) {
+    // Algorithm 2's geometric buckets: ends floor((C + delta)(1 + delta)^(i+1)),
+    // the product by repeated multiplication in double precision, while they
+    // fit 32 bits; a bucket is processed at most
+    // floor(ln n_r / ln(1 + delta / C)) + 1 rounds (Lemma 2: each round leaves
+    // at most a C / (C + delta) share of the r-cliques of the bucket's core
+    // range outside it)
+    uint64_t C = 1;   // C(s, r)
+    for (uint32_t i = 0; i < c->r; i++) C = C * (c->s - i) / (i + 1);
+    const double d = c->approx_delta;
+    uint32_t host_thr[4096];
+    uint32_t nt = 0;
+    double t = (double)C + d;
+    while (nt < 4096) {
+      t *= 1.0 + d;
+      if (t >= 4294967296.0) break;
+      host_thr[nt++] = (uint32_t)t;
+    }
+    if (nt == 0) return nd_fail(c, ND_E_OVERFLOW, "approximate buckets exceed 32 bits");
+    uint32_t *dthr = (uint32_t *)nd_buf(c, B_THR, nt * 4ull, &st);
+    if (!dthr) return st;
+    if ((st = nd_hip(c, hipMemcpyAsync(dthr, host_thr, nt * 4ull, hipMemcpyHostToDevice,
+                                       c->stream), "bucket ends")) != ND_OK)
+      return st;
+    pa.thr = dthr;
+    pa.n_thr = nt;
+    uint64_t cap = 1;
+    if (nr > 1) cap = (uint64_t)(std::log((double)nr) / std::log(1.0 + d / (double)C)) + 1;
+    pa.round_cap = (uint32_t)std::min<uint64_t>(cap, 0xFFFFFFFFull);
+    c->info.round_cap = pa.round_cap;
   }
   pa.sc = sc;
   pa.progress = c->progress;

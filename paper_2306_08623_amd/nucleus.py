@@ -52,7 +52,7 @@ EXPORTS = [
     "nd_server_create", "nd_server_destroy", "nd_server_submit", "nd_server_poll",
     "nd_server_wait", "nd_server_get", "nd_server_release", "nd_server_cancel",
     "nd_server_get_stats", "nd_server_last_error",
-    "nd_cut", "nd_get_cut",
+    "nd_cut", "nd_get_cut", "nd_set_approx",
     "nd_status_str", "nd_last_error",
 ]
 
@@ -104,6 +104,8 @@ class Info(C.Structure):
         ("cascades", C.c_uint64),
         ("cas_retries", C.c_uint64),
         ("device_peak", C.c_uint64),
+        ("approx_delta", C.c_double),
+        ("round_cap", C.c_uint32),
     ]
 
     def as_dict(self) -> dict:
@@ -276,6 +278,8 @@ def load_library(path: str = LIB_PATH):
     lib.nd_server_get_stats.restype = C.c_int
     lib.nd_server_last_error.argtypes = [vp]
     lib.nd_server_last_error.restype = C.c_char_p
+    lib.nd_set_approx.argtypes = [vp, C.c_double]
+    lib.nd_set_approx.restype = C.c_int
     lib.nd_cut.argtypes = [vp, C.c_uint32, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
     lib.nd_cut.restype = C.c_int
     lib.nd_get_cut.argtypes = [vp, vp, vp, vp, C.c_int]
@@ -453,6 +457,19 @@ class Context:
         self._check(self.lib.nd_get_tree(self.h, parent.ctypes.data if parent.size else None,
                                          level.ctypes.data if level.size else None, ND_MEM_HOST))
         return parent, level
+
+    def nd_set_approx(self, delta: float):
+        """delta > 0: approximate decomposition (Algorithm 2); 0: exact."""
+        self._check(self.lib.nd_set_approx(self.h, float(delta)))
+
+    def decompose_approx(self, csr, r: int, s: int, delta: float) -> Result:
+        """Approximate core numbers and their hierarchy; the context returns
+        to exact peeling afterwards."""
+        self.nd_set_approx(delta)
+        try:
+            return self.decompose(csr, r, s)
+        finally:
+            self.nd_set_approx(0.0)
 
     def nd_cut(self, c: int) -> tuple[int, int]:
         """Cut the last decomposition's tree at level c: (nuclei, vertices)."""

@@ -63,7 +63,8 @@ def check_cut(ctx, g, r, s, levels, tag):
         rank = np.empty(nn, dtype=np.int64)
         rank[order] = np.arange(nn)
         gl = got["leaf_nucleus"]
-        mapped = np.where(gl >= 0, rank[np.maximum(gl, 0)], -1)
+        mapped = np.full(gl.shape, -1, dtype=np.int64)
+        mapped[gl >= 0] = rank[gl[gl >= 0]]
         assert np.array_equal(mapped, want["leaf_nucleus"]), (tag, c)
         # the vertex lists tile exactly
         assert int(nuc["n_vertices"].sum()) == len(got["verts"])

@@ -112,3 +112,37 @@ def test_rmat18_34_sampled(ctx, rmat18):
     nodes = certify.check_small_nodes_connected(G, parent, level, core, n_r)
     _say(f"[fullsize] rmat18 (3,4): {npairs} adjacent pairs closed, {nodes} small nodes connected")
     G.close()
+
+
+@pytest.mark.timeout(300)
+def test_rmat18_23_approx_bound(ctx, rmat18):
+    """Algorithm 2 at full size: the GPU's exact (2,3) core numbers hash to
+    the oracle's golden values; the approximate ones, for three deltas, lie
+    within the theorem's bound of them on every edge, and take far fewer
+    rounds."""
+    from make_golden import result_hashes
+    with open(os.path.join(HERE, "golden", "rmat18_23.json")) as f:
+        gold = json.load(f)
+    exact = ctx.decompose(rmat18, 2, 3)
+    got = result_hashes(exact.rcliques, exact.counts, exact.coreness, exact.parent, exact.level)
+    assert got["coreness"] == gold["sha256"]["coreness"]
+    core = exact.coreness.astype(np.float64)
+    for delta in (0.1, 0.5, 1.0):
+        _say(f"[fullsize] rmat18 (2,3) approximate, delta={delta}")
+        ap = ctx.decompose_approx(rmat18, 2, 3, delta)
+        apx = ap.coreness.astype(np.float64)
+        assert np.all((core == 0) == (apx == 0))
+        assert np.all(apx >= core)
+        assert np.all(apx <= (3 + delta) * (1 + delta) * core)
+        assert ap.info["rounds"] < exact.info["rounds"]
+        # the tree of the approximate values: a node holds its leaves, so
+        # its level (the smallest value inside) is at most theirs; children
+        # lie above their parents
+        n_r = ap.info["n_r"]
+        parent, level = ap.parent, ap.level.astype(np.int64)
+        leaf_p = parent[:n_r]
+        has = leaf_p != np.iinfo(np.uint64).max
+        assert np.all(level[(leaf_p[has] - n_r).astype(np.int64)] <= ap.coreness[has])
+        ip = parent[n_r:]
+        hp = ip != np.iinfo(np.uint64).max
+        assert np.all(level[(ip[hp] - n_r).astype(np.int64)] < level[hp])
