@@ -422,10 +422,47 @@ nd_status nd_server_get_stats(nd_server *srv, nd_server_stats *out);
 /* Message of the server's last error (empty if none). */
 const char *nd_server_last_error(const nd_server *srv);
 
+/* ---- Decomposition without device allocation ---------------------------
+ *
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. The same
+ * pipeline and kernels as nd_load_csr + nd_set_rs + nd_decompose +
+ * nd_get_coreness / nd_get_tree (results identical), but every intermediate
+ * buffer lives in one fixed device array of ND_NOALLOC_SCRATCH_BYTES per GPU
+ * (the library reserves it, on every GPU it runs on, until the process
+ * ends); no device memory is allocated or freed, not even on first use.
+ *
+ *   device, hip_stream  GPU ordinal and the hipStream_t to run on (NULL =
+ *                       null stream); the call returns after the stream
+ *                       finished its work.
+ *   n, nnz, row_ptr, col  the CSR, as for nd_load_csr, in DEVICE memory of
+ *                       that GPU (validated on the device).
+ *   r, s                as for nd_set_rs.
+ *   cap                 capacity of the outputs, in r-cliques.
+ *   coreness            device uint32[cap]: core numbers (nd_get_coreness).
+ *   parent, level       device uint64[2 cap] / uint32[cap]: the canonical
+ *                       tree (nd_get_tree; n_r + n_int <= 2 n_r - 1 nodes).
+ *   info                host, may be NULL: the run's nd_info (n_r, n_int ...).
+ *
+ * Errors: ND_E_OOM when the graph does not fit the scratch (the CSR and its
+ * edge ids alone must take at most ND_NOALLOC_SCRATCH_BYTES; larger tables
+ * are found as the pipeline sizes them), ND_E_INVALID_ARG when n_r > cap
+ * (info still tells n_r), and every error of the calls it stands for. The
+ * message is nd_last_error(NULL) on the calling thread. Calls on one GPU
+ * share its scratch, which keeps the last call's contents; the library runs
+ * them one at a time (a second caller waits), so they never overlap there.
+ * Graphs up to about 10^5 edges fit for s = 3, fewer triangles for s = 4. */
+#define ND_NOALLOC_SCRATCH_BYTES (64ull << 20)
+nd_status nd_decompose_noalloc(int device, void *hip_stream, uint32_t n, uint64_t nnz,
+                               const uint64_t *row_ptr, const uint32_t *col, uint32_t r,
+                               uint32_t s, uint64_t cap, uint32_t *coreness, uint64_t *parent,
+                               uint32_t *level, nd_info *info);
+
 const char *nd_status_str(nd_status st);
 
 /* Message of the last error of this context (empty string if none). With
- * ctx == NULL: the message of the last failed nd_create on this thread. */
+ * ctx == NULL: the message of the last failed nd_create or
+ * nd_decompose_noalloc on this thread. */
 const char *nd_last_error(const nd_ctx *ctx);
 
 #ifdef __cplusplus

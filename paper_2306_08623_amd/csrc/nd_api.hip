@@ -207,8 +207,15 @@ const char *nd_status_str(nd_status st) {
   return "unknown status";
 }
 
-// message of the last failed nd_create on this thread (no context exists)
+// message of the last failed nd_create or nd_decompose_noalloc on this
+// thread (no context of the caller's exists)
 static thread_local std::string g_create_error;
+
+}  // extern "C"
+
+void nd_thread_error(const char *msg) { g_create_error = msg; }
+
+extern "C" {
 
 const char *nd_last_error(const nd_ctx *c) {
   return c ? c->last_error.c_str() : g_create_error.c_str();

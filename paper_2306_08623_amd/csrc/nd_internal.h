@@ -431,6 +431,8 @@ struct DevScalars {
 // helpers implemented in nd_api.hip
 nd_status nd_fail(nd_ctx *c, nd_status st, const std::string &msg);
 void *nd_buf(nd_ctx *c, int id, size_t bytes, nd_status *st);
+// sets the message nd_last_error(NULL) returns on this thread
+void nd_thread_error(const char *msg);
 // forgets every buffer of an arena context (its memory is reused from the
 // start by the next nd_buf calls); the caller ensures no queued work uses it
 void nd_arena_reset(nd_ctx *c);

@@ -51,10 +51,13 @@ EXPORTS = [
     "nd_get_tree", "nd_batch_decompose", "nd_batch_get", "nd_estimate_footprint",
     "nd_server_create", "nd_server_destroy", "nd_server_submit", "nd_server_poll",
     "nd_server_wait", "nd_server_get", "nd_server_release", "nd_server_cancel",
-    "nd_server_get_stats", "nd_server_last_error",
+    "nd_server_get_stats", "nd_server_last_error", "nd_decompose_noalloc",
     "nd_cut", "nd_get_cut", "nd_set_approx",
     "nd_status_str", "nd_last_error",
 ]
+
+# fixed device scratch of nd_decompose_noalloc, per GPU (include/nucleus.h)
+ND_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class Options(C.Structure):
@@ -278,6 +281,10 @@ def load_library(path: str = LIB_PATH):
     lib.nd_server_get_stats.restype = C.c_int
     lib.nd_server_last_error.argtypes = [vp]
     lib.nd_server_last_error.restype = C.c_char_p
+    lib.nd_decompose_noalloc.argtypes = [C.c_int, vp, C.c_uint32, C.c_uint64, vp, vp,
+                                         C.c_uint32, C.c_uint32, C.c_uint64, vp, vp, vp,
+                                         C.POINTER(Info)]
+    lib.nd_decompose_noalloc.restype = C.c_int
     lib.nd_set_approx.argtypes = [vp, C.c_double]
     lib.nd_set_approx.restype = C.c_int
     lib.nd_cut.argtypes = [vp, C.c_uint32, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]
@@ -562,6 +569,27 @@ class Context:
 def decompose(csr, r: int, s: int, device: int = 0, **opts) -> Result:
     with Context(device=device, **opts) as ctx:
         return ctx.decompose(csr, r, s)
+
+
+def decompose_noalloc(n: int, row_ptr, col, r: int, s: int, coreness, parent, level,
+                      device: int = 0, stream=None) -> dict:
+    """nd_decompose_noalloc: device tensors in (CSR) and out (coreness
+    uint32[cap], parent uint64[2 cap], level uint32[cap]); the library
+    allocates no device memory. Returns the run's nd_info."""
+    lib = load_library()
+    if stream is None:
+        stream = _current_stream(device)
+    cap = int(coreness.numel())
+    if int(parent.numel()) < 2 * cap or int(level.numel()) < cap:
+        raise ValueError("parent needs 2 * cap entries and level cap entries")
+    info = Info()
+    st = lib.nd_decompose_noalloc(device, stream, n, int(col.numel()), row_ptr.data_ptr(),
+                                  col.data_ptr(), r, s, cap, coreness.data_ptr(),
+                                  parent.data_ptr(), level.data_ptr(), C.byref(info))
+    if st != ND_OK:
+        msg = lib.nd_last_error(None).decode() or lib.nd_status_str(st).decode()
+        raise NucleusError(st, msg)
+    return info.as_dict()
 
 
 def _host_desc(csr, r: int, s: int):
