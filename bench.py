@@ -264,7 +264,8 @@ def bench_batch(count: int, reps: int) -> dict:
 def bench_serve(pool_size: int, count: int, rates: list[float], workers: int) -> dict:
     """Serving: Poisson arrivals of requests drawn from a pool of seeded
     Chung-Lu / R-MAT graphs (1K-2M edges, (r,s) from {(1,2),(2,3),(3,4)}).
-    For every rate: p50/p99 latency (submit to results ready, server clock)
+    For every rate: p50/p99 latency (submit to results ready on the device,
+    server clock; and submit to results downloaded to the host, host clock)
     and completed graphs/s. Capacity (all requests submitted at once) is
     compared with a one-request-at-a-time server on the same requests."""
     import threading
@@ -286,6 +287,7 @@ def bench_serve(pool_size: int, count: int, rates: list[float], workers: int) ->
         with nucleus.Server(device=0, workers=n_workers, max_batch=max_batch) as srv:
             tickets = [0] * n_req
             lag = np.zeros(n_req)
+            t_submit_host = np.zeros(n_req)
             submitted = [threading.Event() for _ in range(n_req)]
 
             errors = []
@@ -299,6 +301,7 @@ def bench_serve(pool_size: int, count: int, rates: list[float], workers: int) ->
                             time.sleep(wait)
                         lag[i] = time.perf_counter() - start - arrive[i]
                         g, r, s = pool[i % len(pool)]
+                        t_submit_host[i] = time.perf_counter()
                         tickets[i] = srv.submit(g, r, s)
                         submitted[i].set()
                 except Exception as e:          # surfaced by the collector below
@@ -308,28 +311,54 @@ def bench_serve(pool_size: int, count: int, rates: list[float], workers: int) ->
 
             th = threading.Thread(target=submitter)
             th.start()
-            infos = []
-            for i in range(n_req):           # collect and release as results come
-                submitted[i].wait()
+            # collect results as they complete (any order): poll the
+            # outstanding tickets, download each finished one to the host
+            infos = [None] * n_req
+            t_sub = np.zeros(n_req)
+            t_got = np.zeros(n_req)
+            pending = []
+            nxt = 0
+            while nxt < n_req or pending:
+                while nxt < n_req and submitted[nxt].is_set():
+                    if errors:
+                        raise errors[0]
+                    t_sub[nxt] = t_submit_host[nxt]
+                    pending.append(nxt)
+                    nxt += 1
+                progressed = False
+                for i in list(pending):
+                    info = srv.poll(tickets[i])
+                    if not info["done"]:
+                        continue
+                    if info["status"] != nucleus.ND_OK:
+                        raise RuntimeError(f"request {i} failed: {info}")
+                    srv.get(tickets[i], pool[i % len(pool)][1])   # results to the host
+                    t_got[i] = time.perf_counter()
+                    srv.release(tickets[i])
+                    infos[i] = info
+                    pending.remove(i)
+                    progressed = True
                 if errors:
                     raise errors[0]
-                info = srv.wait(tickets[i])
-                if info["status"] != nucleus.ND_OK:
-                    raise RuntimeError(f"request {i} failed: {info}")
-                infos.append(info)
-                srv.release(tickets[i])
+                if not progressed:
+                    time.sleep(0.0005)
             th.join()
             st = srv.stats()
         lat = np.array([x["t_done_ms"] - x["t_submit_ms"] for x in infos])
+        e2e = (t_got - t_sub) * 1e3
         t_first = min(x["t_submit_ms"] for x in infos)
         t_last = max(x["t_done_ms"] for x in infos)
         return {
             "rate_req_s": rate, "requests": n_req,
             "graphs_per_s": n_req / ((t_last - t_first) * 1e-3),
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "p50_with_download_ms": float(np.percentile(e2e, 50)),
+            "p99_with_download_ms": float(np.percentile(e2e, 99)),
             "mean_batch": float(np.mean([x["batch_size"] for x in infos])),
             "submit_lag_p99_ms": float(np.percentile(lag, 99) * 1e3),
             "batches": st["batches"], "overlapped": st["overlapped"],
+            "device_overlap_ms": round(st["device_overlap_ms"], 3),
+            "device_busy_ms": round(st["device_busy_ms"], 3),
         }
 
     out = {"workload": f"inputs.serve_graph(i, 5000000), i < {pool_size}: m log-uniform in "
@@ -433,6 +462,70 @@ def measure(name: str, r: int, s: int, steps: int, warmup: int, peel_blocks: int
     }
 
 
+def bench_cut_and_approx(name: str, r: int, s: int, delta: float, cpu_scale: int) -> dict:
+    """The two query-side rows on the benched graph: the hierarchy cut (the
+    c-(r,s) nuclei with vertex sets and induced edges) at five levels, and
+    the approximate decomposition (Algorithm 2) against the exact one; the
+    oracle's components-from-definition and approximate decomposition on the
+    same scaled-down sample as the baseline."""
+    import torch
+
+    from paper_2306_08623_amd import nucleus
+
+    g, _ = workload(name)
+    out = {}
+    with nucleus.Context(device=0) as ctx:
+        ctx.load_csr(g)
+        ctx.nd_set_rs(r, s)
+        ctx.nd_decompose()
+        info = ctx.nd_get_info()
+        k = info["k"]
+        cuts = []
+        for c in sorted({1, max(1, k // 4), max(1, k // 2), max(1, 3 * k // 4), max(1, k)}):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            nn, nv = ctx.nd_cut(c)
+            dt = time.perf_counter() - t0
+            cuts.append({"c": c, "nuclei": nn, "vertices": nv, "ms": round(dt * 1e3, 3)})
+        out["cut"] = {"levels": cuts, "k": k}
+        print(f"[bench] cut: {cuts}", file=sys.stderr, flush=True)
+        exact_rounds = info["rounds"]
+        ctx.nd_set_approx(delta)
+        ctx.nd_decompose()                      # warm-up of the approximate mode
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.nd_decompose()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ai = ctx.nd_get_info()
+        ctx.nd_set_approx(0.0)
+        out["approx"] = {"delta": delta, "ms": round(dt * 1e3, 3), "rounds": ai["rounds"],
+                         "exact_rounds": exact_rounds, "k": ai["k"], "exact_k": k,
+                         "round_cap": ai["round_cap"],
+                         "phases_ms": {"prep": round(ai["ms_prep"], 3),
+                                       "count": round(ai["ms_count"], 3),
+                                       "peel": round(ai["ms_peel"], 3),
+                                       "tree": round(ai["ms_tree"], 3)}}
+        print(f"[bench] approx delta={delta}: {dt:.3f} s, {ai['rounds']} rounds "
+              f"(exact {exact_rounds})", file=sys.stderr, flush=True)
+    if cpu_scale:
+        import oracle
+        gs, what = cpu_sample(name, cpu_scale)
+        d = oracle.decompose(gs, r, s)
+        c = max(1, int(d.k) // 2)
+        x = oracle.nuclei(gs, r, s, d.coreness, c)
+        t0 = time.perf_counter()
+        a = oracle.approx_decompose(gs, r, s, delta)
+        ta = time.perf_counter() - t0
+        out["cut"]["cpu_oracle"] = {"c": c, "nuclei": x["n_nuclei"], "seconds": x["seconds"],
+                                    "cores": 1, "kind": "oracle",
+                                    "sample": f"components of core >= c, no tree, on {what}"}
+        out["approx"]["cpu_oracle"] = {"seconds": round(ta, 3), "exact_seconds":
+                                       round(d.t_count + d.t_peel + d.t_tree, 3), "cores": 1,
+                                       "kind": "oracle", "sample": what}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -447,6 +540,9 @@ def main() -> int:
                     help="the oracle baseline runs on the workload's generator at a size "
                          "reduced by 2^scale (R-MAT: scale lower by this much) (0: skip)")
     ap.add_argument("--peel-blocks", type=int, default=0)
+    ap.add_argument("--queries", type=int, default=1,
+                    help="hierarchy cut and approximate decomposition objects (0: skip)")
+    ap.add_argument("--delta", type=float, default=0.5)
     ap.add_argument("--batch", type=int, default=4096,
                     help="graphs in the batched-vs-one-by-one comparison (0: skip)")
     ap.add_argument("--batch-reps", type=int, default=2)
@@ -491,6 +587,8 @@ def main() -> int:
     if args.secondary:
         out["secondary"] = measure(args.secondary, r, s, args.secondary_steps, 1,
                                    args.peel_blocks)
+    if args.queries:
+        out.update(bench_cut_and_approx(args.workload, r, s, args.delta, args.cpu_scale))
     if args.batch:
         out["batch"] = bench_batch(args.batch, args.batch_reps)
     if args.serve:

@@ -107,6 +107,11 @@ typedef struct nd_options {
  * them), EL for (1,2), (2,3), (3,4). */
 #define ND_FLAG_HIER_EL 2u
 #define ND_FLAG_HIER_TE 4u
+/* s = 4 counting keeps a row's common out-neighbourhood (at most its
+ * out-degree) in on-chip memory when that is at most 1024, else in a slice
+ * of global memory per wave (about 1 GiB in all). This flag sends every
+ * row to the global slices (the same counts; for testing that path). */
+#define ND_FLAG_COUNT_GLOBAL 8u
 
 /* Per-decomposition statistics. Counters are totals over the whole run. */
 typedef struct nd_info {
@@ -197,10 +202,10 @@ nd_status nd_set_approx(nd_ctx *ctx, double delta);
  * 20 s without progress instead of hanging). Blocks on small readbacks of
  * the r-clique count (needed to size the per-r-clique arrays) and, for s = 4,
  * of the largest out-degree of the orientation (it sizes the counting
- * kernel's on-chip buffers), and at the end; results stay on the device
- * until read with nd_get_*. For s = 4 an orientation whose largest
- * out-degree exceeds 1024 (a graph of degeneracy above 1024) returns
- * ND_E_UNSUPPORTED before counting. */
+ * kernel's buffers: on chip up to 1024, global memory beyond), and at the
+ * end; results stay on the device until read with nd_get_*. A 32-bit count
+ * that would wrap ((1,3), (1,4), (2,4) on very dense graphs) stops the run
+ * with ND_E_UNSUPPORTED. */
 nd_status nd_decompose(nd_ctx *ctx);
 
 /* Wait for the context's stream and report device-side errors. */

@@ -12,7 +12,8 @@
 //   s = 3: one lane per DG edge u -> v; every common out-neighbour w is a
 //          triangle {u, v, w}; edge ids come from the DG slots.
 //   s = 4: one wave per DG edge; the common out-neighbourhood C2 is built in
-//          LDS (ballot compaction keeps it ascending); lanes then test the
+//          LDS (ballot compaction keeps it ascending) -- for rows of
+//          out-degree above 1024, in a global slice of the wave; lanes then test the
 //          pairs {w, x} of C2 for adjacency; every adjacent pair closes a
 //          4-clique {u, v, w, x}. Triangle ids (r = 3) are read from W(e) of
 //          the triangle's lexicographically first edge by binary search.
@@ -23,7 +24,7 @@
 namespace {
 
 constexpr uint32_t kCountBlock = 256;
-constexpr uint32_t kC2Cap = 1024;   // largest C2 (and oriented out-degree) the 4-clique kernel takes
+constexpr uint32_t kC2Cap = 1024;   // largest C2 (oriented out-degree) kept on chip
 
 __global__ void k_count_degree(uint32_t n, const uint64_t *__restrict__ rp,
                                uint32_t *__restrict__ cnt) {
@@ -89,13 +90,23 @@ __global__ void __launch_bounds__(kCountBlock) k_count_s3(GraphView g, uint32_t 
 template <int R>
 constexpr uint32_t count_s4_arrays() { return R == 3 ? 4 : 3; }
 
-template <int R>
+// kGlobal = false: the C2 arrays are in LDS (cap entries per wave) and the
+// kernel takes the edges u -> v whose u has out-degree <= cap; kGlobal =
+// true: they are in global memory (gbuf, one slice of cap entries per wave
+// of the grid) and the kernel takes the edges whose u has out-degree above
+// `light` (those the LDS kernel left; all of them when light = 0).
+template <int R, bool kGlobal>
 __global__ void __launch_bounds__(kCountBlock) k_count_s4(GraphView g, uint32_t *__restrict__ cnt,
-                                                          DevScalars *sc, uint32_t cap) {
+                                                          DevScalars *sc, uint32_t cap,
+                                                          uint32_t *__restrict__ gbuf,
+                                                          uint32_t light) {
   extern __shared__ uint32_t s_c2[];
   const uint32_t wv = threadIdx.x / 64;
   const uint32_t lane = lane_id();
-  uint32_t *cv = s_c2 + (uint64_t)count_s4_arrays<R>() * cap * wv;
+  uint32_t *cv = kGlobal
+      ? gbuf + (uint64_t)count_s4_arrays<R>() * cap *
+                   ((uint64_t)blockIdx.x * (kCountBlock / 64) + wv)
+      : s_c2 + (uint64_t)count_s4_arrays<R>() * cap * wv;
   uint32_t *ceu = cv + cap;
   uint32_t *cev = ceu + cap;
   uint32_t *cn = cev + cap;   // r = 3 only
@@ -103,9 +114,11 @@ __global__ void __launch_bounds__(kCountBlock) k_count_s4(GraphView g, uint32_t 
   const uint64_t nwaves = (uint64_t)gridDim.x * (kCountBlock / 64);
   for (uint64_t j = blockIdx.x * (uint64_t)(kCountBlock / 64) + wv; j < g.m; j += nwaves) {
     const uint32_t u = segment_of(g.dgp, g.n, j);
+    const uint64_t bu = g.dgp[u], eu = g.dgp[u + 1];
+    if (kGlobal ? eu - bu <= light : eu - bu > cap) continue;   // the other kernel's edge
     const uint32_t v = g.dgc[j];
     const uint32_t e_uv = g.dge[j];
-    const uint64_t bu = g.dgp[u], eu = g.dgp[u + 1], bv = g.dgp[v], ev = g.dgp[v + 1];
+    const uint64_t bv = g.dgp[v], ev = g.dgp[v + 1];
     // C2 = N+(u) intersect N+(v), ascending, with the edge ids to u and v
     uint32_t c = 0;
     for (uint64_t base = bu; base < eu; base += 64) {
@@ -134,7 +147,7 @@ __global__ void __launch_bounds__(kCountBlock) k_count_s4(GraphView g, uint32_t 
       }
       c += __popcll(mask);
     }
-    if (c > cap) {   // the host sizes cap to the maximum out-degree, so this cannot happen
+    if (c > cap) {   // C2 is within u's out-row, at most cap entries: cannot happen
       if (lane == 0) atomicOr(&sc->status, ND_DERR_OVERFLOW);
       continue;
     }
@@ -159,17 +172,19 @@ __global__ void __launch_bounds__(kCountBlock) k_count_s4(GraphView g, uint32_t 
       if (p == el) continue;
       local++;
       if (R == 1) {
+        // (1,4) counts are guarded before counting (probe ranges below 2^32)
         atomicAdd(&cnt[u], 1u);
         atomicAdd(&cnt[v], 1u);
         atomicAdd(&cnt[w], 1u);
         atomicAdd(&cnt[x], 1u);
       } else if (R == 2) {
-        atomicAdd(&cnt[e_uv], 1u);
-        atomicAdd(&cnt[ceu[a]], 1u);
-        atomicAdd(&cnt[cev[a]], 1u);
-        atomicAdd(&cnt[ceu[b]], 1u);
-        atomicAdd(&cnt[cev[b]], 1u);
-        atomicAdd(&cnt[g.dge[p]], 1u);
+        // (2,4): an edge's count is at most C(|common neighbours|, 2), which
+        // can pass 2^32: a wrap is caught where it happens
+        const uint32_t e6[6] = {e_uv, ceu[a], cev[a], ceu[b], cev[b], g.dge[p]};
+        bool wrap = false;
+#pragma unroll
+        for (int z = 0; z < 6; z++) wrap |= atomicAdd(&cnt[e6[z]], 1u) == 0xFFFFFFFFu;
+        if (wrap) atomicOr(&sc->status, ND_DERR_OVERFLOW);
       } else {
         // triangles {u,v,w} and {u,v,x} are counted per C2 entry (LDS),
         // {u,w,x} and {v,w,x} per 4-clique
@@ -242,25 +257,52 @@ nd_status nd_stage_count(nd_ctx *c, const GraphView &g) {
         (st = nd_hip(c, hipStreamSynchronize(c->stream), "max out-degree")) != ND_OK)
       return st;
     c->info.max_outdeg = maxd;
-    if (maxd > kC2Cap)
-      return nd_fail(c, ND_E_UNSUPPORTED,
-                     "oriented out-degree exceeds the 4-clique listing buffer (1024)");
-    const uint32_t cap = std::max<uint32_t>(64, (maxd + 63) / 64 * 64);
-    const uint32_t grid = nd_grid(g.m, kCountBlock / 64, 65536);
-    const void *kern = r == 1 ? (const void *)k_count_s4<1>
-                     : r == 2 ? (const void *)k_count_s4<2> : (const void *)k_count_s4<3>;
+    // rows of out-degree up to kC2Cap keep C2 on chip; heavier rows (a
+    // graph of degeneracy above kC2Cap, or every row with
+    // ND_FLAG_COUNT_GLOBAL) keep it in a global slice per wave
+    const bool force_global = (c->flags & ND_FLAG_COUNT_GLOBAL) != 0;
+    const uint32_t light = force_global ? 0u : std::min<uint32_t>(maxd, kC2Cap);
     const uint32_t arrays = r == 1 ? count_s4_arrays<1>()
                           : r == 2 ? count_s4_arrays<2>() : count_s4_arrays<3>();
-    const size_t lds = (size_t)(kCountBlock / 64) * arrays * cap * 4;
-    if ((st = nd_hip(c, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                            (int)lds), "count LDS size")) != ND_OK)
-      return st;
-    if (r == 1)
-      hipLaunchKernelGGL(k_count_s4<1>, dim3(grid), dim3(kCountBlock), lds, c->stream, g, cnt, sc, cap);
-    else if (r == 2)
-      hipLaunchKernelGGL(k_count_s4<2>, dim3(grid), dim3(kCountBlock), lds, c->stream, g, cnt, sc, cap);
-    else
-      hipLaunchKernelGGL(k_count_s4<3>, dim3(grid), dim3(kCountBlock), lds, c->stream, g, cnt, sc, cap);
+    if (light) {
+      const uint32_t cap = std::max<uint32_t>(64, (light + 63) / 64 * 64);
+      const uint32_t grid = nd_grid(g.m, kCountBlock / 64, 65536);
+      const void *kern = r == 1 ? (const void *)k_count_s4<1, false>
+                       : r == 2 ? (const void *)k_count_s4<2, false>
+                                : (const void *)k_count_s4<3, false>;
+      const size_t lds = (size_t)(kCountBlock / 64) * arrays * cap * 4;
+      if ((st = nd_hip(c, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                              (int)lds), "count LDS size")) != ND_OK)
+        return st;
+      if (r == 1)
+        hipLaunchKernelGGL((k_count_s4<1, false>), dim3(grid), dim3(kCountBlock), lds, c->stream,
+                           g, cnt, sc, cap, nullptr, 0u);
+      else if (r == 2)
+        hipLaunchKernelGGL((k_count_s4<2, false>), dim3(grid), dim3(kCountBlock), lds, c->stream,
+                           g, cnt, sc, cap, nullptr, 0u);
+      else
+        hipLaunchKernelGGL((k_count_s4<3, false>), dim3(grid), dim3(kCountBlock), lds, c->stream,
+                           g, cnt, sc, cap, nullptr, 0u);
+    }
+    if (force_global || maxd > kC2Cap) {
+      const uint32_t cap = std::max<uint32_t>(64, (maxd + 63) / 64 * 64);
+      // waves of the global kernel: as many as 1 GiB of C2 slices holds,
+      // between 64 and 65,536
+      const uint64_t per_wave = (uint64_t)arrays * cap * 4;
+      const uint64_t waves = std::max<uint64_t>(64, std::min<uint64_t>(65536, (1ull << 30) / per_wave));
+      uint32_t *gbuf = (uint32_t *)nd_buf(c, B_C2G, waves * per_wave, &st);
+      if (!gbuf) return st;
+      const uint32_t grid = (uint32_t)(waves / (kCountBlock / 64));
+      if (r == 1)
+        hipLaunchKernelGGL((k_count_s4<1, true>), dim3(grid), dim3(kCountBlock), 0, c->stream, g,
+                           cnt, sc, cap, gbuf, light);
+      else if (r == 2)
+        hipLaunchKernelGGL((k_count_s4<2, true>), dim3(grid), dim3(kCountBlock), 0, c->stream, g,
+                           cnt, sc, cap, gbuf, light);
+      else
+        hipLaunchKernelGGL((k_count_s4<3, true>), dim3(grid), dim3(kCountBlock), 0, c->stream, g,
+                           cnt, sc, cap, gbuf, light);
+    }
   }
   st = nd_hip(c, hipGetLastError(), "count kernels");
   if (c->events_ok) (void)hipEventRecord(c->ev[8], c->stream);

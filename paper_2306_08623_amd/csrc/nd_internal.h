@@ -380,6 +380,8 @@ enum BufId : int {
   B_CUT_TOP, B_CUT_POS, B_CUT_LEAF, B_CUT_NUC, B_CUT_RCL, B_CUT_K0, B_CUT_K1, B_CUT_V0,
   B_CUT_V1, B_CUT_FLAG, B_CUT_POS2, B_CUT_VERTS, B_CUT_VNUC, B_CUT_CNT,
   B_THR,   // approximate decomposition: bucket ends
+  B_C2G,   // 4-clique counting: global C2 slices for rows above the LDS cap
+  B_CSLOT, // peel: chunk -> frontier slot map of a large round
   B_COUNT
 };
 

@@ -74,6 +74,10 @@ struct PeelArgs {
   const uint32_t *thr;
   uint32_t n_thr;
   uint32_t round_cap;
+  // chunk map of a large round: the frontier slot holding probe unit 64 c,
+  // for every chunk c (cslot_cap entries at most)
+  uint32_t *cslot;
+  uint64_t cslot_cap;
 };
 
 // ---------------------------------------------------------------------------
@@ -127,23 +131,19 @@ __device__ __forceinline__ void uf_find2(uint32_t *uf, uint32_t &x, uint32_t &y)
   }
 }
 
-// Counts one compare-and-swap that lost a race and is retried (rare: a
-// global atomic only on that path).
-__device__ __forceinline__ void count_retry(uint64_t *retries) {
-  if (retries) atomicAdd((unsigned long long *)retries, 1ull);
-}
-
 // Joins the sets of a and b; the smaller root id survives. Returns the root
 // whose parent pointer this call changed (the loser), or ND_NONE when a and b
-// were already in one set. Lost races are counted into *retries (if given).
+// were already in one set. Lost races are counted in *retries, a counter
+// of the workgroup in LDS (summed into the device scalars once per launch,
+// so counting costs neither registers nor global atomics).
 __device__ __forceinline__ uint32_t uf_unite(uint32_t *uf, uint32_t a, uint32_t b,
-                                             uint64_t *retries = nullptr) {
+                                             uint32_t *retries) {
   for (;;) {
     uf_find2(uf, a, b);
     if (a == b) return ND_NONE;
     if (a > b) { uint32_t t = a; a = b; b = t; }
     if (cas32(&uf[b], b, a)) return b;
-    count_retry(retries);
+    atomicAdd(retries, 1u);
   }
 }
 
@@ -155,6 +155,7 @@ struct LinkCtx {
   uint32_t linkq_cap;
   DevScalars *sc;
   uint64_t links, unites;
+  uint32_t *retries;  // LDS: compare-and-swaps of unite / L that lost a race
 };
 
 // The spill queue is a ring of linkq_cap (a power of two) pairs addressed by
@@ -197,7 +198,7 @@ __device__ __forceinline__ uint32_t link_step(LinkCtx &c, uint32_t R, uint32_t Q
   }
   if (ndR == ndQ) {
     if (R == Q) return 0;
-    const uint32_t loser = uf_unite(c.uf, R, Q, &c.sc->cas_retries);   // hand-over as in link_efficient
+    const uint32_t loser = uf_unite(c.uf, R, Q, c.retries);   // hand-over as in link_efficient
     if (loser != ND_NONE) {
       c.unites++;
       const uint32_t w = uf_find(c.uf, loser);
@@ -218,7 +219,7 @@ __device__ __forceinline__ uint32_t link_step(LinkCtx &c, uint32_t R, uint32_t Q
         if (pQ != Q) push(R, pQ);
         return no;
       }
-      count_retry(&c.sc->cas_retries);
+      atomicAdd(c.retries, 1u);
       continue;
     }
     if (c.nd[LQ] < ndR) {
@@ -228,7 +229,7 @@ __device__ __forceinline__ uint32_t link_step(LinkCtx &c, uint32_t R, uint32_t Q
         push(R, LQ);
         return no;
       }
-      count_retry(&c.sc->cas_retries);
+      atomicAdd(c.retries, 1u);
     } else {
       push(R, LQ);
       return no;
@@ -324,7 +325,7 @@ __device__ void link_efficient(LinkCtx &c, uint32_t R0, uint32_t Q0) {
       // case unite joins their current roots, and it is one of those whose L
       // must move (a CAS on L[loser] that lands after this read is handed
       // over by its own writer, which then sees loser is no longer a root).
-      const uint32_t loser = uf_unite(c.uf, R, Q, &c.sc->cas_retries);
+      const uint32_t loser = uf_unite(c.uf, R, Q, c.retries);
       if (loser != ND_NONE) {
         c.unites++;
         const uint32_t w = uf_find(c.uf, loser);
@@ -349,7 +350,7 @@ __device__ void link_efficient(LinkCtx &c, uint32_t R0, uint32_t Q0) {
             if (pQ != Q) push(R, pQ);   // Q was merged meanwhile
             break;
           }
-          count_retry(&c.sc->cas_retries);
+          atomicAdd(c.retries, 1u);
           continue;                      // L[Q] was set concurrently: read again
         }
         if (c.nd[LQ] < ndR) {
@@ -359,7 +360,7 @@ __device__ void link_efficient(LinkCtx &c, uint32_t R0, uint32_t Q0) {
             push(R, LQ);
             break;
           }
-          count_retry(&c.sc->cas_retries);
+          atomicAdd(c.retries, 1u);
         } else {
           push(R, LQ);
           break;
@@ -744,6 +745,9 @@ __global__ void __launch_bounds__(kPeelBlock, 5) k_peel(PeelArgs a) {
   lc.sc = sc;
   lc.links = 0;
   lc.unites = 0;
+  __shared__ uint32_t s_retries;
+  if (threadIdx.x == 0) s_retries = 0;
+  lc.retries = &s_retries;
   uint64_t visits = 0, decs = 0, scans = 0, calls = 0;
   for (uint32_t i = threadIdx.x; i < kLinkCache; i += kPeelBlock) s_lcache[i] = ~0ull;
   if (!residency_gate(sc->bar, nb, &sc->status)) return;
@@ -957,6 +961,22 @@ __global__ void __launch_bounds__(kPeelBlock, 5) k_peel(PeelArgs a) {
       __syncthreads();
     }
     const uint64_t P = s_boff[nb];
+    // A large round first maps every chunk of 64 probe units to the frontier
+    // slot of its first unit (each slot writes the chunks that start inside
+    // it; one more grid barrier), so a lane finds its slot from the map in a
+    // short search instead of a block search and a slot search. Small rounds
+    // skip the map: the barrier would cost more than it saves.
+    const uint64_t nchunks = (P + 63) >> 6;
+    const bool use_map = P >= 16ull * nthreads && nchunks <= a.cslot_cap;
+    if (use_map) {
+      const uint64_t ub = s_boff[blockIdx.x];
+      for (uint64_t i = sbeg + threadIdx.x; i < send; i += kPeelBlock) {
+        const uint64_t u0 = ub + (i > sbeg ? a.wscan[i - 1] : 0);
+        const uint64_t u1 = ub + a.wscan[i];
+        for (uint64_t ch = (u0 + 63) >> 6; (ch << 6) < u1; ch++) a.cslot[ch] = (uint32_t)i;
+      }
+      if (!grid_barrier(sc->bar, nb, &sc->status)) break;
+    }
     uint64_t *wq = s_lq[kLink ? wv : 0];
     uint32_t qn = 0;   // pending link steps of this wave (uniform)
     uint32_t seg_hint = 0;   // this lane's segment in its previous pass (units only grow)
@@ -971,7 +991,26 @@ __global__ void __launch_bounds__(kPeelBlock, 5) k_peel(PeelArgs a) {
         push[j] = false;
         lpair[j] = ~0ull;
       }
-      if (p < P) {
+      uint32_t R = 0, idx = 0;
+      bool have = false;
+      if (p < P && use_map) {
+        // the slot holding p lies between the slots of p's chunk and of the
+        // next chunk: the last slot there whose first unit is <= p
+        const uint64_t ch = p >> 6;
+        uint64_t lo = a.cslot[ch];
+        uint64_t hi = ch + 1 < nchunks ? (uint64_t)a.cslot[ch + 1] + 1 : f;
+        auto start = [&](uint64_t i) -> uint64_t {
+          const uint64_t blk = i / seg;
+          return s_boff[blk] + (i > blk * seg ? a.wscan[i - 1] : 0);
+        };
+        while (hi - lo > 1) {
+          const uint64_t mid = (lo + hi) >> 1;
+          if (start(mid) <= p) lo = mid;
+          else hi = mid;
+        }
+        R = F[lo];
+        idx = (uint32_t)(p - start(lo));
+      } else if (p < P) {
         // block segment holding unit p (s_boff[lo] <= p < s_boff[hi]): a
         // binary search in the first pass, a gallop from the previous
         // segment after it; then the frontier slot inside the segment
@@ -1004,59 +1043,60 @@ __global__ void __launch_bounds__(kPeelBlock, 5) k_peel(PeelArgs a) {
             else x1 = mid;
           }
         }
-        const uint32_t R = F[x0];
+        R = F[x0];
         const uint64_t before = (x0 > b0) ? a.wscan[x0 - 1] : 0;
-        const uint32_t idx = (uint32_t)(qoff - before);
-        if (Sh::visit(g, R, idx, others)) {
-          visits++;
-          uint32_t rr[NO];   // peel states
-          bool dead = false, lead = true;
+        idx = (uint32_t)(qoff - before);
+      }
+      have = p < P;
+      if (have && Sh::visit(g, R, idx, others)) {
+        visits++;
+        uint32_t rr[NO];   // peel states
+        bool dead = false, lead = true;
 #pragma unroll
-          for (int j = 0; j < NO; j++) {
-            rr[j] = a.pst[others[j]];
-            dead |= rr[j] == kPeeledBefore;
-            lead &= !(rr[j] == kPeeledNow && others[j] < R);
-          }
-          // decrements first; their old values are only compared after the
-          // link checks below, so the atomics stay in flight meanwhile
-          uint32_t oldc[NO];
-          bool dec[NO];
-#pragma unroll
-          for (int j = 0; j < NO; j++) {
-            dec[j] = !dead && lead && rr[j] == kAlive;
-            oldc[j] = 0;
-            if (dec[j]) {
-              oldc[j] = atomicSub(&a.cnt[others[j]], 1u);
-              decs++;
-            }
-          }
-          uint32_t qroot = ND_NONE;   // cache key of R's set, formed on first use
-#pragma unroll
-          for (int j = 0; j < NO; j++) {
-            if (kLink && (rr[j] == kPeeledBefore || (rr[j] == kPeeledNow && R < others[j]))) {
-              uint32_t x = others[j];
-              if (qroot == ND_NONE) {
-                qroot = R;
-                key_root2(a.uf, qroot, x);
-              } else {
-                x = key_root(a.uf, x);
-              }
-              if (x == qroot || lcache_hit(s_lcache, x, qroot)) continue;
-              const uint64_t key = ((uint64_t)x << 32) | qroot;
-              uint64_t *gslot = &a.gcache[gcache_slot(x, qroot, a.gcache_mask)];
-              if (*gslot == key) {
-                lcache_put(s_lcache, x, qroot);
-                continue;
-              }
-              calls++;
-              lpair[j] = ((uint64_t)others[j] << 32) | R;
-              lcache_put(s_lcache, x, qroot);
-              atomicExch((unsigned long long *)gslot, (unsigned long long)key);
-            }
-          }
-#pragma unroll
-          for (int j = 0; j < NO; j++) push[j] = dec[j] && oldc[j] == k + 1;
+        for (int j = 0; j < NO; j++) {
+          rr[j] = a.pst[others[j]];
+          dead |= rr[j] == kPeeledBefore;
+          lead &= !(rr[j] == kPeeledNow && others[j] < R);
         }
+        // decrements first; their old values are only compared after the
+        // link checks below, so the atomics stay in flight meanwhile
+        uint32_t oldc[NO];
+        bool dec[NO];
+#pragma unroll
+        for (int j = 0; j < NO; j++) {
+          dec[j] = !dead && lead && rr[j] == kAlive;
+          oldc[j] = 0;
+          if (dec[j]) {
+            oldc[j] = atomicSub(&a.cnt[others[j]], 1u);
+            decs++;
+          }
+        }
+        uint32_t qroot = ND_NONE;   // cache key of R's set, formed on first use
+#pragma unroll
+        for (int j = 0; j < NO; j++) {
+          if (kLink && (rr[j] == kPeeledBefore || (rr[j] == kPeeledNow && R < others[j]))) {
+            uint32_t x = others[j];
+            if (qroot == ND_NONE) {
+              qroot = R;
+              key_root2(a.uf, qroot, x);
+            } else {
+              x = key_root(a.uf, x);
+            }
+            if (x == qroot || lcache_hit(s_lcache, x, qroot)) continue;
+            const uint64_t key = ((uint64_t)x << 32) | qroot;
+            uint64_t *gslot = &a.gcache[gcache_slot(x, qroot, a.gcache_mask)];
+            if (*gslot == key) {
+              lcache_put(s_lcache, x, qroot);
+              continue;
+            }
+            calls++;
+            lpair[j] = ((uint64_t)others[j] << 32) | R;
+            lcache_put(s_lcache, x, qroot);
+            atomicExch((unsigned long long *)gslot, (unsigned long long)key);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < NO; j++) push[j] = dec[j] && oldc[j] == k + 1;
       }
 #pragma unroll
       for (int j = 0; j < NO; j++) {
@@ -1103,6 +1143,9 @@ __global__ void __launch_bounds__(kPeelBlock, 5) k_peel(PeelArgs a) {
   // statistics
   uint64_t v = wave_sum64(visits), d = wave_sum64(decs), l = wave_sum64(lc.links),
            u = wave_sum64(lc.unites), cl = wave_sum64(calls);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_retries)
+    atomicAdd((unsigned long long *)&sc->cas_retries, (unsigned long long)s_retries);
   if (lane == 0) {
     if (cl) atomicAdd((unsigned long long *)&sc->link_calls, (unsigned long long)cl);
     if (v) atomicAdd((unsigned long long *)&sc->visits, (unsigned long long)v);
@@ -1149,30 +1192,30 @@ struct HierArgs {
 };
 
 __device__ __forceinline__ void hier_pair(const HierArgs &a, uint32_t R, uint32_t R2, uint32_t c,
-                                          uint64_t &unites) {
+                                          uint64_t &unites, uint32_t *retries) {
   const uint32_t n2 = a.nd[R2];
   if (n2 == c) {   // same core: one component, one tree
-    unites += uf_unite(a.uf, R, R2, &a.sc->cas_retries) != ND_NONE;
-    uf_unite(a.tuf, R, R2, &a.sc->cas_retries);
+    unites += uf_unite(a.uf, R, R2, retries) != ND_NONE;
+    uf_unite(a.tuf, R, R2, retries);
     return;
   }
   const uint32_t T = uf_find(a.tuf, R2);
   const uint32_t B = ld_acq32(&a.bottom[T]);
   if (a.nd[B] == c) {   // R2's tree already hangs below a core-c component
-    unites += uf_unite(a.uf, B, R, &a.sc->cas_retries) != ND_NONE;
-    uf_unite(a.tuf, T, R, &a.sc->cas_retries);
+    unites += uf_unite(a.uf, B, R, retries) != ND_NONE;
+    uf_unite(a.tuf, T, R, retries);
     return;
   }
   // R2's tree still ends at a component of a higher core: hang it below R
   const uint32_t Bs = uf_find(a.uf, B);   // final: that core is finished
   const uint32_t old = atomicCAS(&a.L[Bs], ND_NONE, R);
   if (old == ND_NONE) {
-    uf_unite(a.tuf, T, R, &a.sc->cas_retries);
+    uf_unite(a.tuf, T, R, retries);
     const uint32_t w = uf_find(a.tuf, R);
     __hip_atomic_store(&a.bottom[w], R, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   } else {   // taken at this level by the component of `old`
-    unites += uf_unite(a.uf, old, R, &a.sc->cas_retries) != ND_NONE;
-    uf_unite(a.tuf, T, R, &a.sc->cas_retries);
+    unites += uf_unite(a.uf, old, R, retries) != ND_NONE;
+    uf_unite(a.tuf, T, R, retries);
   }
 }
 
@@ -1191,6 +1234,9 @@ __global__ void __launch_bounds__(kPeelBlock) k_hier(HierArgs a) {
   const uint64_t gtid = blockIdx.x * (uint64_t)kPeelBlock + threadIdx.x;
   const uint64_t nthreads = (uint64_t)nb * kPeelBlock;
   uint64_t visits = 0, pairs = 0, unites = 0;
+  __shared__ uint32_t s_retries;
+  if (threadIdx.x == 0) s_retries = 0;
+  uint32_t *retries = &s_retries;
   if (!residency_gate(sc->bar, nb, &sc->status)) return;
 
   for (uint32_t c = a.k; c >= 1; c--) {
@@ -1271,7 +1317,7 @@ __global__ void __launch_bounds__(kPeelBlock) k_hier(HierArgs a) {
           for (int j = 0; j < NO; j++) {
             if (a.nd[others[j]] >= c) {
               pairs++;
-              hier_pair(a, R, others[j], c, unites);
+              hier_pair(a, R, others[j], c, unites, retries);
             }
           }
         }
@@ -1280,6 +1326,9 @@ __global__ void __launch_bounds__(kPeelBlock) k_hier(HierArgs a) {
     if (!grid_barrier(sc->bar, nb, &sc->status)) break;
   }
   const uint64_t v = wave_sum64(visits), l = wave_sum64(pairs), u = wave_sum64(unites);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_retries)
+    atomicAdd((unsigned long long *)&sc->cas_retries, (unsigned long long)s_retries);
   if (lane == 0) {
     if (v) atomicAdd((unsigned long long *)&sc->hier_visits, (unsigned long long)v);
     if (l) atomicAdd((unsigned long long *)&sc->links, (unsigned long long)l);
@@ -1451,6 +1500,10 @@ nd_status nd_stage_peel(nd_ctx *c, const GraphView &g) {
     if ((st = nd_hip(c, hipMemsetAsync(pa.gcache, 0xFF, ge * 8, c->stream), "gcache")) != ND_OK)
       return st;
   }
+  // chunk map of large rounds (one entry per 64 probe units of a round);
+  // rounds with more chunks fall back to the two searches
+  pa.cslot_cap = nr / 2 + (1u << 20);
+  if (!(pa.cslot = (uint32_t *)nd_buf(c, B_CSLOT, pa.cslot_cap * 4, &st))) return st;
   if (c->approx_delta > 0) {
     // Algorithm 2's geometric buckets: ends floor((C + delta)(1 + delta)^(i+1)),
     // the product by repeated multiplication in double precision, while they

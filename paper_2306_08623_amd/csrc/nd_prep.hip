@@ -606,6 +606,15 @@ __global__ void k_t14_len(uint64_t nnz, const uint64_t *__restrict__ rp,
   }
 }
 
+// a vertex's triangles ((1,3): its s-clique count and probe range) must
+// stay below 2^32
+__global__ void k_t13_check(uint32_t n, const uint64_t *__restrict__ rp,
+                            const uint64_t *__restrict__ sg, uint32_t *status) {
+  for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n;
+       v += (uint64_t)gridDim.x * blockDim.x)
+    if (sg[rp[v + 1]] - sg[rp[v]] >= 0xFFFFFFFFull) atomicOr(status, ND_DERR_OVERFLOW);
+}
+
 // a vertex's (1,4) probe range must stay below 2^32 entries
 __global__ void k_t14_check(uint32_t n, const uint64_t *__restrict__ rp,
                             const uint64_t *__restrict__ sg, const uint64_t *__restrict__ tg,
@@ -790,6 +799,9 @@ nd_status nd_stage_prep(nd_ctx *c, GraphView *gv) {
       uint64_t total = 0;
       st = nd_exclusive_scan_u32_to_u64(c, scnt, sgl, nnz, &total);
       if (st != ND_OK) return st;
+      if (n)
+        hipLaunchKernelGGL(k_t13_check, dim3(nd_grid(n, 256, 16384)), dim3(256), 0, c->stream, n,
+                           rp, sgl, &sc->status);
       gv->sg = sgl;
       if (c->s == 4) {
         // (1,4): for every triangle probe (v, w, x) of (1,3), the probed part

@@ -41,6 +41,7 @@ ND_MEM_DEVICE = 1
 ND_FLAG_PROGRESS = 1
 ND_FLAG_HIER_EL = 2
 ND_FLAG_HIER_TE = 4
+ND_FLAG_COUNT_GLOBAL = 8
 
 NONE64 = np.uint64(0xFFFFFFFFFFFFFFFF)
 
@@ -333,7 +334,7 @@ class Context:
     def __init__(self, device: int = 0, stream=None, validate: bool = True, mem_limit: int = 0,
                  peel_blocks: int = 0, work_chunk: int = 0, watchdog: int = 0,
                  use_torch_stream: bool = True, progress: bool = False,
-                 hierarchy: str = "auto", allocator: str = "hip"):
+                 hierarchy: str = "auto", allocator: str = "hip", count_global: bool = False):
         """allocator: "hip" (the library's own hipMalloc) or "torch" (PyTorch's
         caching allocator through the nd_options callbacks)."""
         self.lib = load_library()
@@ -348,7 +349,8 @@ class Context:
         opt.work_chunk = work_chunk
         opt.watchdog = watchdog
         opt.flags = (ND_FLAG_PROGRESS if progress else 0) | \
-            {"auto": 0, "el": ND_FLAG_HIER_EL, "te": ND_FLAG_HIER_TE}[hierarchy]
+            {"auto": 0, "el": ND_FLAG_HIER_EL, "te": ND_FLAG_HIER_TE}[hierarchy] | \
+            (ND_FLAG_COUNT_GLOBAL if count_global else 0)
         self._alloc_cbs = None
         if allocator == "torch":
             if torch is None or not torch.cuda.is_available():

@@ -130,15 +130,39 @@ def test_error_paths(ctx):
     check(ctx, I.complete(6), 2, 3, "after-errors")
 
 
-def test_outdegree_limit(ctx):
-    """For s = 4 an orientation whose largest out-degree exceeds 1024 (the
-    4-clique counter's buffers) is rejected before counting: K_1026 has
-    degeneracy 1025. The context stays usable."""
-    from paper_2306_08623_amd import nucleus
-    with pytest.raises(nucleus.NucleusError) as e:
-        ctx.decompose(I.complete(1026), 3, 4)
-    assert e.value.code == nucleus.ND_E_UNSUPPORTED
+def _bipartite_plus_clique(a: int, q: int):
+    """K_{a,a} plus a clique on q vertices of each side: an orientation with
+    out-degree above 1024 (degeneracy about a) whose s-cliques all touch
+    the planted clique."""
+    left = list(range(a))
+    right = list(range(a, 2 * a))
+    edges = [(u, v) for u in left for v in right]
+    planted = left[:q] + right[:q]
+    edges += [(planted[i], planted[j]) for i in range(len(planted))
+              for j in range(i + 1, len(planted))]
+    return I.from_edges(2 * a, edges)
+
+
+def test_outdegree_above_lds_cap(ctx):
+    """s = 4 on a graph whose oriented out-degree passes 1024 (the on-chip
+    C2 buffer): the heavy rows go to the global-memory counter; results
+    equal the oracle's. The context stays usable."""
+    g = _bipartite_plus_clique(1030, 4)
+    for r, s in [(3, 4), (2, 4), (1, 4)]:
+        res, d = check(ctx, g, r, s, "K1030,1030+K8")
+        assert res.info["max_outdeg"] > 1024
     check(ctx, I.complete(7), 3, 4, "after-outdegree-limit")
+
+
+@pytest.mark.parametrize("r,s", [(3, 4), (2, 4), (1, 4)])
+def test_count_global_c2(r, s):
+    """Every row through the global-memory C2 slices (ND_FLAG_COUNT_GLOBAL):
+    the same counts, cores and trees as the oracle."""
+    from paper_2306_08623_amd import nucleus
+    with nucleus.Context(device=0, count_global=True) as c2:
+        for g, name in [(I.workload_er2k(), "er2k"), (I.rmat(12, 16, seed=7), "rmat12"),
+                        (I.complete(9), "K9"), (I.two_k5_bridge(), "two-K5")]:
+            check(c2, g, r, s, f"{name}/global-C2")
 
 
 def test_progress_reports(capfd):
