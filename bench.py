@@ -76,7 +76,7 @@ def measured_traffic(kernel: str, workload_name: str, r: int, s: int):
         return None
     text = open(path).read()
     src = os.path.join(ROOT, "paper_2306_08623_amd", "csrc")
-    files = {"k_peel": ("nd_peel.hip", "nd_internal.h"),
+    files = {"k_peel": ("nd_peel_kern.h", "nd_internal.h"),
              "k_count_s4": ("nd_count.hip", "nd_internal.h")}.get(kernel)
     if files is None:
         return None
@@ -217,7 +217,18 @@ def bench_batch(count: int, reps: int) -> dict:
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - tb) / reps
     binfo = ctx.nd_get_info()
-    print(f"[bench] batch: batched {t_batch:.3f} s per batch", file=sys.stderr, flush=True)
+    print(f"[bench] batch: batched {t_batch:.3f} s per batch (tuned schedules: "
+          f"{len(nucleus.load_schedules())} entries)", file=sys.stderr, flush=True)
+    # the same batch with the default grid (no schedule table)
+    with nucleus.Context(device=0, validate=False, schedule="none") as uctx:
+        uctx.nd_batch_decompose(descs, results, nucleus.ND_MEM_DEVICE)   # warm-up
+        torch.cuda.synchronize()
+        tu = time.perf_counter()
+        for rep in range(reps):
+            uctx.nd_batch_decompose(descs, results, nucleus.ND_MEM_DEVICE)
+        torch.cuda.synchronize()
+        t_untuned = (time.perf_counter() - tu) / reps
+    print(f"[bench] batch: untuned {t_untuned:.3f} s per batch", file=sys.stderr, flush=True)
     lib = ctx.lib
     # one by one: same context kind, same device-resident inputs
     for (n, rp, col, r, s, nnz) in dev[:8]:                             # warm-up
@@ -251,6 +262,8 @@ def bench_batch(count: int, reps: int) -> dict:
         "total_m": int(sum(g.m for g, _, _ in graphs)),
         "total_n_r": int(total_nr), "total_n_s": int(total_ns),
         "batched_graphs_per_s": count / t_batch,
+        "batched_untuned_graphs_per_s": count / t_untuned,
+        "schedule_entries": len(nucleus.load_schedules()),
         "one_by_one_graphs_per_s": count / t_one,
         "speedup": t_one / t_batch,
         "batched_s": t_batch, "one_by_one_s": t_one, "reps": reps,

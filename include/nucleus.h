@@ -80,7 +80,8 @@ typedef struct nd_options {
   int validate;           /* nonzero: check the CSR on the device             */
   uint64_t mem_limit;     /* max bytes of device workspace; 0 = no limit      */
   uint32_t peel_blocks;   /* workgroups of the persistent peel launch; 0=auto */
-  uint32_t work_chunk;    /* probe elements per lane task (>=1); 0 = auto     */
+  uint32_t work_chunk;    /* reserved, ignored: the peel hands out one probe
+                             element per lane and pass                        */
   uint64_t watchdog;      /* max peel rounds before ND_E_WATCHDOG; 0 = auto   */
   uint32_t flags;         /* ND_FLAG_* bits                                   */
   /* Where the context's device workspace comes from: both NULL = hipMalloc /
@@ -170,9 +171,16 @@ void nd_destroy(nd_ctx *ctx);
 nd_status nd_load_csr(nd_ctx *ctx, uint32_t n, uint64_t nnz, const uint64_t *row_ptr,
                       const uint32_t *col, nd_mem where);
 
-/* Choose (r,s): supported pairs are every 1 <= r < s <= 4: (1,2) (k-core),
- * (2,3) (k-truss), (1,3), (1,4), (2,4), (3,4). Pairs with s > 4 return
- * ND_E_UNSUPPORTED; r < 1 or r >= s returns ND_E_INVALID_ARG. */
+/* Choose (r,s): every 1 <= r < s <= 7 (Section 3 defines the decomposition
+ * for any pair; the paper's evaluation runs r < s <= 7), e.g. (1,2)
+ * (k-core), (2,3) (k-truss), (3,4). Pairs with s <= 4 find the s-cliques
+ * containing an r-clique again from edge -> triangle lists whenever they are
+ * needed; pairs with s = 5..7 list every s-clique once and keep the
+ * r-clique / s-clique incidence in device memory (8 C(s,r) bytes per
+ * s-clique, plus the clique levels up to s while they are listed), so their
+ * size is bounded by the device's memory (ND_E_OOM) and by 32-bit r- and
+ * s-clique ids (ND_E_OVERFLOW). s > 7 returns ND_E_UNSUPPORTED; r < 1 or
+ * r >= s returns ND_E_INVALID_ARG. */
 nd_status nd_set_rs(nd_ctx *ctx, uint32_t r, uint32_t s);
 
 /* Approximate decomposition (Section 6, Algorithm 2): with delta > 0 the
@@ -193,6 +201,31 @@ nd_status nd_set_rs(nd_ctx *ctx, uint32_t r, uint32_t s);
  * [0, 64], else ND_E_INVALID_ARG. Bucket ends that would pass 2^32 - 1
  * stop the run with ND_E_UNSUPPORTED. */
 nd_status nd_set_approx(nd_ctx *ctx, double delta);
+
+/* Schedules: the persistent peel's grid size (workgroups) by kind, (r,s)
+ * and size. The grid changes no result (only which lanes do which work): a
+ * small grid makes each of the peel's grid barriers cheaper (a run has
+ * thousands of rounds, two or three barriers each), a large one gives big
+ * rounds more lanes. An entry applies to decompositions of its kind (a
+ * single graph, or the disjoint union of one (r,s) group of a batch) of
+ * pair (r,s) with at most n_r_max r-cliques; the first matching entry in
+ * table order wins. The entries are written by an autotuner that times
+ * candidate grids on the device (paper_2306_08623_amd/autotune.py, table
+ * paper_2306_08623_amd/schedules.json). */
+#define ND_SCHED_SINGLE 0u
+#define ND_SCHED_BATCH 1u
+typedef struct nd_schedule {
+  uint32_t r, s;
+  uint64_t n_r_max;       /* largest n_r the entry applies to                 */
+  uint32_t peel_blocks;   /* workgroups of the persistent peel; 0 = resident
+                             capacity of the device                           */
+  uint32_t kind;          /* ND_SCHED_SINGLE or ND_SCHED_BATCH                */
+} nd_schedule;
+
+/* Replace the context's schedule table (copied; n = 0 clears it). An
+ * nd_options.peel_blocks other than 0 overrides every entry. Entries with
+ * r < 1, s <= r, s > 7 or an unknown kind are ND_E_INVALID_ARG. */
+nd_status nd_set_schedule(nd_ctx *ctx, const nd_schedule *table, uint32_t n);
 
 /* Run the whole pipeline on the context's stream: orientation, r-clique
  * tables, s-clique counting, peel rounds with linking, tree construction and
@@ -320,7 +353,9 @@ nd_status nd_batch_get(nd_ctx *ctx, uint32_t i, uint32_t *rcliques, uint32_t *co
 /* Device-memory estimate of decomposing one graph, from its size and a
  * bound on its clique counts (the number of r-cliques, and of triangles
  * where the tables need them, bounded from the degree sequence: each edge
- * {u,v} lies in at most min(deg u, deg v) - 1 triangles). workspace: bytes
+ * {u,v} lies in at most min(deg u, deg v) - 1 triangles; for s = 5..7 every
+ * k-clique level up to s is bounded by sum_v C(deg v, k - 1) / k, which is
+ * loose on graphs with hubs). workspace: bytes
  * the pipeline holds while the graph runs (alone or as part of a batch
  * union, plus 4 MiB per batch); result: bytes of its outputs. Reads the CSR
  * on the host (device inputs are copied back first). Either output may be

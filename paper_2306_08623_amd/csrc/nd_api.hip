@@ -353,6 +353,17 @@ nd_status nd_set_approx(nd_ctx *c, double delta) {
   return ND_OK;
 }
 
+nd_status nd_set_schedule(nd_ctx *c, const nd_schedule *table, uint32_t n) {
+  if (!c) return ND_E_INVALID_ARG;
+  if (n && !table) return nd_fail(c, ND_E_INVALID_ARG, "NULL schedule table");
+  for (uint32_t i = 0; i < n; i++)
+    if (table[i].r < 1 || table[i].s <= table[i].r || table[i].s > kMaxS ||
+        table[i].kind > ND_SCHED_BATCH)
+      return nd_fail(c, ND_E_INVALID_ARG, "schedule entry with an invalid (r,s) or kind");
+  c->sched.assign(table, table + n);
+  return ND_OK;
+}
+
 nd_status nd_set_rs(nd_ctx *c, uint32_t r, uint32_t s) {
   if (!c) return ND_E_INVALID_ARG;
   if (r < 1 || s <= r) return nd_fail(c, ND_E_INVALID_ARG, "need 1 <= r < s");

@@ -68,6 +68,23 @@ __global__ void k_tri_offsets(uint64_t n_tri, const uint32_t *__restrict__ te,
   }
 }
 
+// the same from a lexicographic r-clique table (s = 5..7, r >= 2): a
+// graph's r-cliques start at the first tuple whose first vertex is its own
+__global__ void k_rcl_offsets(uint64_t n_r, uint32_t r, const uint32_t *__restrict__ rcl,
+                              const uint64_t *__restrict__ voff, uint32_t G,
+                              uint64_t *__restrict__ roff) {
+  for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g <= G; g += gridDim.x * blockDim.x) {
+    const uint64_t v = voff[g];
+    uint64_t lo = 0, hi = n_r;
+    while (lo < hi) {
+      const uint64_t mid = (lo + hi) >> 1;
+      if (rcl[mid * r] < v) lo = mid + 1;
+      else hi = mid;
+    }
+    roff[g] = lo;
+  }
+}
+
 // graph of every union node (by its smallest leaf) as a sort key
 __global__ void k_node_keys(uint64_t n_int, const uint32_t *__restrict__ node_ml,
                             const uint64_t *__restrict__ roff, uint32_t G,
@@ -265,7 +282,10 @@ static nd_status run_group(nd_ctx *c, int gi, BatchGroup &B, const nd_graph_desc
   c->s = B.s;
   c->have_graph = true;
   if (c->validate && (st = nd_validate_loaded(c)) != ND_OK) return st;
-  if ((st = nd_run_pipeline(c)) != ND_OK) return st;
+  c->in_batch = true;
+  st = nd_run_pipeline(c);
+  c->in_batch = false;
+  if (st != ND_OK) return st;
 
   // ---- per-graph offsets of r-cliques
   const uint64_t n_r = c->n_r, n_int = c->n_int;
@@ -302,9 +322,13 @@ static nd_status run_group(nd_ctx *c, int gi, BatchGroup &B, const nd_graph_desc
   } else if (B.r == 2) {
     for (uint32_t j = 0; j <= G; j++) B.roff[j] = eoff[j] / 2;
   }
-  if (B.r == 3) {
-    hipLaunchKernelGGL(k_tri_offsets, dim3(nd_grid(G + 1, 256, 1024)), dim3(256), 0, c->stream,
-                       n_r, c->gv.te, c->gv.eu, d_voff, G, d_roff);
+  if (B.r >= 3) {
+    if (c->gv.rcl)
+      hipLaunchKernelGGL(k_rcl_offsets, dim3(nd_grid(G + 1, 256, 1024)), dim3(256), 0, c->stream,
+                         n_r, B.r, c->gv.rcl, d_voff, G, d_roff);
+    else
+      hipLaunchKernelGGL(k_tri_offsets, dim3(nd_grid(G + 1, 256, 1024)), dim3(256), 0, c->stream,
+                         n_r, c->gv.te, c->gv.eu, d_voff, G, d_roff);
     if ((st = nd_hip(c, hipMemcpyAsync(B.roff.data(), d_roff, (G + 1) * 8, hipMemcpyDeviceToHost,
                                        c->stream),
                      "roff")) != ND_OK)
@@ -441,7 +465,7 @@ nd_status nd_batch_plan(uint32_t G, const nd_graph_desc *graphs, nd_mem where,
     *err = "graph " + std::to_string(i) + ": " + what;
     return code;
   };
-  bool present[kBatchGroups] = {false, false, false, false, false, false};
+  bool present[kBatchGroups] = {};
   for (uint32_t i = 0; i < G; i++) {
     const nd_graph_desc &d = graphs[i];
     if (d.r < 1 || d.s <= d.r) return fail_graph(i, ND_E_INVALID_ARG, "need 1 <= r < s");
@@ -453,8 +477,8 @@ nd_status nd_batch_plan(uint32_t G, const nd_graph_desc *graphs, nd_mem where,
     if (d.n == 0 && d.nnz) return fail_graph(i, ND_E_BAD_GRAPH, "edges without vertices");
     if (where == ND_MEM_HOST && (d.row_ptr[0] != 0 || d.row_ptr[d.n] != d.nnz))
       return fail_graph(i, ND_E_BAD_GRAPH, "row_ptr[0] must be 0 and row_ptr[n] must be nnz");
-    // groups in the fixed order (1,2), (2,3), (3,4), (2,4): each pair keeps
-    // its own result slots from one batch to the next
+    // groups in the fixed order of nd_rs_index: each pair keeps its own
+    // result slots from one batch to the next
     const int pi = nd_rs_index(d.r, d.s);
     present[pi] = true;
     bs->loc[i] = {(uint32_t)pi, 0};
@@ -464,10 +488,12 @@ nd_status nd_batch_plan(uint32_t G, const nd_graph_desc *graphs, nd_mem where,
     gidx[p] = (uint32_t)bs->groups.size();
     if (present[p]) {
       bs->groups.emplace_back();
-      static const uint32_t kR[kBatchGroups] = {1, 2, 3, 2, 1, 1};
-      static const uint32_t kS[kBatchGroups] = {2, 3, 4, 4, 3, 4};
-      bs->groups.back().r = kR[p];
-      bs->groups.back().s = kS[p];
+      for (uint32_t s = 2; s <= kMaxS; s++)
+        for (uint32_t r = 1; r < s; r++)
+          if (nd_rs_index(r, s) == (int)p) {
+            bs->groups.back().r = r;
+            bs->groups.back().s = s;
+          }
       bs->groups.back().slot = (int)p;
     }
   }

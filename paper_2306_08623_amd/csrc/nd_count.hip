@@ -87,6 +87,12 @@ __global__ void __launch_bounds__(kCountBlock) k_count_s3(GraphView g, uint32_t 
 // to v, and for r = 3 the 4-cliques found so far through the triangle
 // {u, v, w} of each entry (its id is looked up when that count is flushed,
 // only for entries that have 4-cliques)
+__global__ void k_count_inc(uint64_t nr, const uint64_t *__restrict__ io, uint32_t *__restrict__ cnt) {
+  for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < nr;
+       x += (uint64_t)gridDim.x * blockDim.x)
+    cnt[x] = (uint32_t)(io[x + 1] - io[x]);
+}
+
 template <int R>
 constexpr uint32_t count_s4_arrays() { return R == 3 ? 4 : 3; }
 
@@ -164,6 +170,27 @@ __global__ void __launch_bounds__(kCountBlock) k_count_s4(GraphView g, uint32_t 
         b = a + 1 + over;
       }
       const uint32_t w = cv[a], x = cv[b];
+      if (R == 3) {
+        // x is a neighbour of u and of v; it lies in W(uw), the common
+        // neighbours of u and w, exactly when w and x are adjacent, and its
+        // slot there names triangle {u, w, x}; its slot in W(vw) names
+        // {v, w, x}. Both lists hold v or u, so neither is empty; the two
+        // searches advance in lockstep.
+        const uint32_t euw = ceu[a], evw = cev[a];
+        const uint64_t b1 = g.wp[euw], f1 = g.wp[euw + 1], b2 = g.wp[evw], f2 = g.wp[evw + 1];
+        uint64_t p1, p2;
+        find2_u32<uint64_t>(g.wc, b1, f1, b2, f2, x, p1, p2);
+        if (p1 == f1) continue;   // w and x are not adjacent
+        local++;
+        // triangles {u,v,w} and {u,v,x} are counted per C2 entry (LDS),
+        // {u,w,x} and {v,w,x} per 4-clique
+        atomicAdd(&cn[a], 1u);
+        atomicAdd(&cn[b], 1u);
+        atomicAdd(&cnt[g.wt[p1]], 1u);
+        if (p2 == f2) atomicOr(&sc->status, ND_DERR_BADGRAPH);   // tables disagree
+        else atomicAdd(&cnt[g.wt[p2]], 1u);
+        continue;
+      }
       // adjacency of w and x through the out-row of the lower-key vertex
       uint32_t lowv = w, highv = x;
       if (g.okey[x] < g.okey[w]) { lowv = x; highv = w; }
@@ -185,19 +212,6 @@ __global__ void __launch_bounds__(kCountBlock) k_count_s4(GraphView g, uint32_t 
 #pragma unroll
         for (int z = 0; z < 6; z++) wrap |= atomicAdd(&cnt[e6[z]], 1u) == 0xFFFFFFFFu;
         if (wrap) atomicOr(&sc->status, ND_DERR_OVERFLOW);
-      } else {
-        // triangles {u,v,w} and {u,v,x} are counted per C2 entry (LDS),
-        // {u,w,x} and {v,w,x} per 4-clique
-        const uint32_t e_wx = g.dge[p];
-        atomicAdd(&cn[a], 1u);
-        atomicAdd(&cn[b], 1u);
-        const uint32_t t2[2] = {tri_lookup(g, u, w, x, ceu[a], ceu[b], e_wx),
-                                tri_lookup(g, v, w, x, cev[a], cev[b], e_wx)};
-#pragma unroll
-        for (int z = 0; z < 2; z++) {
-          if (t2[z] == ND_NONE) atomicOr(&sc->status, ND_DERR_BADGRAPH);
-          else atomicAdd(&cnt[t2[z]], 1u);
-        }
       }
     }
     if (R == 3) {
@@ -235,7 +249,18 @@ nd_status nd_stage_count(nd_ctx *c, const GraphView &g) {
   }
   const uint32_t r = c->r, s = c->s;
   if (c->events_ok) (void)hipEventRecord(c->ev[7], c->stream);
-  if (s == 2) {
+  if (nd_rs_general(s)) {
+    // s = 5..7: the s-cliques were listed once in prep; a count is the
+    // length of the r-clique's incidence list
+    if (nr)
+      hipLaunchKernelGGL(k_count_inc, dim3(nd_grid(nr, 256, 16384)), dim3(256), 0, c->stream, nr,
+                         g.io, cnt);
+    const uint64_t ns = c->gen_n_s;
+    st = nd_hip(c, hipMemcpyAsync(&sc->n_s, &ns, 8, hipMemcpyHostToDevice, c->stream), "n_s");
+    if (st != ND_OK) return st;
+    st = nd_hip(c, hipStreamSynchronize(c->stream), "n_s");
+    if (st != ND_OK) return st;
+  } else if (s == 2) {
     if (g.n)
       hipLaunchKernelGGL(k_count_degree, dim3(nd_grid(g.n, 256, 8192)), dim3(256), 0, c->stream,
                          g.n, g.rp, cnt);

@@ -60,6 +60,15 @@ struct GraphView {
   // W(vw), 1 = W(vx), 2 = W(wx)), and the running sum of the parts' lengths
   const uint32_t *tsel;
   const uint64_t *tg;
+  // s = 5..7 (nd_gen.hip): the s-cliques kept in HBM. rcl: the n_r
+  // lexicographic r-tuples (r >= 2); sm: the nsm = C(s,r) r-clique ids of
+  // every s-clique; io / il: the s-cliques of every r-clique (CSR, [n_r + 1]
+  // offsets)
+  const uint32_t *rcl;
+  const uint32_t *sm;
+  const uint64_t *io;
+  const uint32_t *il;
+  uint32_t nsm;
 };
 
 // ---------------------------------------------------------------------------
@@ -311,6 +320,8 @@ struct nd_ctx {
   uint64_t mem_limit = 0;
   uint32_t peel_blocks = 0;
   uint32_t work_chunk = 0;
+  std::vector<nd_schedule> sched;   // nd_set_schedule: peel grid by (kind, r, s, n_r)
+  bool in_batch = false;            // the pipeline runs a batch group's union
   uint64_t watchdog = 0;
   uint32_t flags = 0;          // ND_FLAG_*
   // persistent grids take 1/grid_div of the device, so that as many
@@ -355,6 +366,7 @@ struct nd_ctx {
   nd_info info{};
   uint64_t n_r = 0;
   uint64_t n_int = 0;
+  uint64_t gen_n_s = 0;   // s = 5..7: s-cliques listed by nd_prep_general
   // last hierarchy cut (nd_cut): valid until the next decomposition
   bool cut_valid = false;
   uint64_t cut_nuclei = 0, cut_verts = 0;
@@ -382,6 +394,10 @@ enum BufId : int {
   B_THR,   // approximate decomposition: bucket ends
   B_C2G,   // 4-clique counting: global C2 slices for rows above the LDS cap
   B_CSLOT, // peel: chunk -> frontier slot map of a large round
+  // s = 5..7 (nd_gen.hip): clique levels, sorted tuples, r-clique table,
+  // s-clique members and the incidence CSR
+  B_GEN_L0, B_GEN_L1, B_GEN_CNT, B_GEN_OFF, B_GEN_RTUP, B_GEN_STUP, B_GEN_RCL, B_GEN_SM,
+  B_GEN_IO, B_GEN_IL,
   B_COUNT
 };
 
@@ -391,21 +407,24 @@ enum BufId : int {
 // EL otherwise
 inline bool nd_use_te(const nd_ctx *c);
 
-// the (r,s) pairs whose peel is built; index of a pair's batch slots
-inline bool nd_rs_supported(uint32_t r, uint32_t s) {
-  return (r == 1 && s == 2) || (r == 2 && s == 3) || (r == 3 && s == 4) || (r == 2 && s == 4) ||
-         (r == 1 && s == 3) || (r == 1 && s == 4);
-}
+// the (r,s) pairs whose peel is built: every 1 <= r < s <= 7 (s <= 4 with
+// edge -> triangle lists, s = 5..7 with the s-cliques kept); index of a
+// pair's batch slots
+constexpr uint32_t kMaxS = 7;
+inline bool nd_rs_supported(uint32_t r, uint32_t s) { return r >= 1 && r < s && s <= kMaxS; }
+inline bool nd_rs_general(uint32_t s) { return s >= 5; }
 inline int nd_rs_index(uint32_t r, uint32_t s) {
   if (r == 2 && s == 4) return 3;
   if (r == 1 && s == 3) return 4;
   if (r == 1 && s == 4) return 5;
-  return (int)r - 1;
+  if (s <= 4) return (int)r - 1;
+  // s = 5..7: after the six pairs above, in (s, r) order
+  return 6 + (int)((s - 5) * (s + 2) / 2) + (int)r - 1;   // s = 5: 6..9, 6: 10..14, 7: 15..20
 }
 
 // batch arena: per (r,s) group, kBatchFields grow-only slots after B_COUNT
 constexpr int kBatchFields = 10;
-constexpr int kBatchGroups = 6;   // (1,2), (2,3), (3,4), (2,4), (1,3), (1,4)
+constexpr int kBatchGroups = 21;   // every pair r < s <= 7
 inline int nd_batch_slot(int group, int field) { return B_COUNT + group * kBatchFields + field; }
 
 // device scalars block (one per context)
@@ -471,6 +490,7 @@ nd_status nd_validate_loaded(nd_ctx *c);
 
 // pipeline stages (each returns ND_OK or an error already recorded in ctx)
 nd_status nd_stage_prep(nd_ctx *c, GraphView *gv);
+nd_status nd_prep_general(nd_ctx *c, GraphView *gv);
 nd_status nd_stage_count(nd_ctx *c, const GraphView &gv);
 nd_status nd_stage_peel(nd_ctx *c, const GraphView &gv);
 nd_status nd_stage_tree(nd_ctx *c, const GraphView &gv);

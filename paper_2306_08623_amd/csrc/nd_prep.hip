@@ -746,12 +746,16 @@ nd_status nd_stage_prep(nd_ctx *c, GraphView *gv) {
   gv->wt = nullptr;
   gv->te = nullptr;
 
-  const bool tri_tables = c->r == 3 || (c->r == 2 && c->s == 4) || (c->r == 1 && c->s >= 3);
   gv->wg = nullptr;
   gv->wsel = nullptr;
   gv->sg = nullptr;
   gv->tsel = nullptr;
   gv->tg = nullptr;
+  if (nd_rs_general(c->s)) {
+    if ((st = nd_hip(c, hipGetLastError(), "prep kernels")) != ND_OK) return st;
+    return nd_prep_general(c, gv);
+  }
+  const bool tri_tables = c->r == 3 || (c->r == 2 && c->s == 4) || (c->r == 1 && c->s >= 3);
   if (tri_tables && m) {
     uint32_t *sup = (uint32_t *)nd_buf(c, B_SUP, m * 4, &st);
     if (!sup) return st;

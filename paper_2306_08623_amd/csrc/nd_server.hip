@@ -68,8 +68,36 @@ void estimate(uint32_t n, uint64_t nnz, const uint64_t *rp, const uint32_t *col,
     }
     tri = sum / 3;
   }
+  if (s >= 5) {
+    // s = 5..7 keep their s-cliques: k-cliques are bounded by
+    // sum_v C(deg v, k - 1) / k (each k-clique is k vertices with k - 1
+    // common neighbours); the tables hold every level up to s, the sorted
+    // r- and s-tuples, the r-clique table and its sort, and 8 C(s,r) bytes
+    // per s-clique
+    const double cap = 4.0e18;
+    double nk[8] = {0, (double)n, (double)m, 0, 0, 0, 0, 0};
+    for (uint32_t k = 3; k <= s; k++) {
+      double t = 0;
+      for (uint32_t v = 0; v < n; v++) {
+        const double d = (double)(rp[v + 1] - rp[v]);
+        double b = 1;   // C(d, k - 1)
+        for (uint32_t i = 0; i < k - 1; i++) b = b * (d - i) / (i + 1);
+        if (b > 0) t += b;
+      }
+      nk[k] = t / k < cap ? t / k : cap;
+    }
+    double C = 1;
+    for (uint32_t i = 0; i < r; i++) C = C * (s - i) / (i + 1);
+    double w = 56.0 * (n + 1) + 32.0 * m + (153.0 + 8.0 * r) * nk[r] + 64;
+    for (uint32_t k = 2; k <= s; k++) w += (4.0 * k + 12.0) * nk[k];
+    w += (8.0 * r + 24.0) * nk[r] + 4.0 * s * nk[s] + 8.0 * C * nk[s] + 8.0 * nk[r];
+    const double res_b = nk[r] * (4.0 * r + 28.0) + 256;
+    if (ws) *ws = w < cap ? (uint64_t)w : (uint64_t)cap;
+    if (res) *res = res_b < cap ? (uint64_t)res_b : (uint64_t)cap;
+    return;
+  }
   const uint64_t n_r = r == 1 ? n : (r == 2 ? m : tri);
-  uint64_t w = 56ull * (n + 1) + 32ull * m + (151ull + 8ull * r) * n_r + 64;
+  uint64_t w = 56ull * (n + 1) + 32ull * m + (153ull + 8ull * r) * n_r + 64;
   if (s >= 3) w += 24ull * (m + 1) + 36ull * tri;
   if (r == 2 && s == 4) w += 48ull * tri;   // probe parts, lengths, running sums
   if (r == 1 && s >= 3) w += 24ull * (m + 1);   // per-slot triangle counts and sums

@@ -371,6 +371,9 @@ nd_status nd_stage_tree(nd_ctx *c, const GraphView &g) {
 
 nd_status nd_write_rcliques(nd_ctx *c, const GraphView &g, uint32_t *out_dev) {
   if (c->n_r == 0) return ND_OK;
+  if (g.rcl)   // s = 5..7, r >= 2: the lexicographic table built in prep
+    return nd_hip(c, hipMemcpyAsync(out_dev, g.rcl, c->n_r * c->r * 4ull, hipMemcpyDeviceToDevice,
+                                    c->stream), "rclique copy");
   hipLaunchKernelGGL(k_rcliques, dim3(nd_grid(c->n_r, kTB, 16384)), dim3(kTB), 0, c->stream, c->r,
                      c->n_r, g.eu, g.ev, g.te, out_dev);
   return nd_hip(c, hipGetLastError(), "rclique kernel");

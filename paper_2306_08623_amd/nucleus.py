@@ -53,7 +53,7 @@ EXPORTS = [
     "nd_server_create", "nd_server_destroy", "nd_server_submit", "nd_server_poll",
     "nd_server_wait", "nd_server_get", "nd_server_release", "nd_server_cancel",
     "nd_server_get_stats", "nd_server_last_error", "nd_decompose_noalloc",
-    "nd_cut", "nd_get_cut", "nd_set_approx",
+    "nd_cut", "nd_get_cut", "nd_set_approx", "nd_set_schedule",
     "nd_status_str", "nd_last_error",
 ]
 
@@ -127,6 +127,26 @@ class Nucleus(C.Structure):
 NUCLEUS_DTYPE = np.dtype([("node", "<u8"), ("min_leaf", "<u8"), ("n_rcliques", "<u8"),
                           ("n_vertices", "<u8"), ("n_edges", "<u8"), ("vert_off", "<u8"),
                           ("level", "<u4"), ("reserved", "<u4")])
+
+
+class Schedule(C.Structure):
+    _fields_ = [("r", C.c_uint32), ("s", C.c_uint32), ("n_r_max", C.c_uint64),
+                ("peel_blocks", C.c_uint32), ("kind", C.c_uint32)]
+
+
+ND_SCHED_SINGLE = 0
+ND_SCHED_BATCH = 1
+SCHEDULES_PATH = os.path.join(_HERE, "schedules.json")
+
+
+def load_schedules(path: str = SCHEDULES_PATH) -> list[dict]:
+    """The autotuned schedule table (entries {kind, r, s, n_r_max,
+    peel_blocks}), or [] if none has been written."""
+    import json
+    if not os.path.exists(path):
+        return []
+    with open(path) as f:
+        return json.load(f)["entries"]
 
 
 class GraphDesc(C.Structure):
@@ -241,6 +261,8 @@ def load_library(path: str = LIB_PATH):
     lib.nd_destroy.restype = None
     lib.nd_load_csr.argtypes = [vp, C.c_uint32, C.c_uint64, vp, vp, C.c_int]
     lib.nd_load_csr.restype = C.c_int
+    lib.nd_set_schedule.argtypes = [vp, C.POINTER(Schedule), C.c_uint32]
+    lib.nd_set_schedule.restype = C.c_int
     lib.nd_set_rs.argtypes = [vp, C.c_uint32, C.c_uint32]
     lib.nd_set_rs.restype = C.c_int
     lib.nd_decompose.argtypes = [vp]
@@ -334,9 +356,12 @@ class Context:
     def __init__(self, device: int = 0, stream=None, validate: bool = True, mem_limit: int = 0,
                  peel_blocks: int = 0, work_chunk: int = 0, watchdog: int = 0,
                  use_torch_stream: bool = True, progress: bool = False,
-                 hierarchy: str = "auto", allocator: str = "hip", count_global: bool = False):
+                 hierarchy: str = "auto", allocator: str = "hip", count_global: bool = False,
+                 schedule="tuned"):
         """allocator: "hip" (the library's own hipMalloc) or "torch" (PyTorch's
-        caching allocator through the nd_options callbacks)."""
+        caching allocator through the nd_options callbacks). schedule:
+        "tuned" (the autotuned table in schedules.json, if present), "none",
+        or a list of entries {kind, r, s, n_r_max, peel_blocks}."""
         self.lib = load_library()
         opt = Options()
         opt.device = device
@@ -367,6 +392,18 @@ class Context:
             raise NucleusError(st, msg)
         self.h = h
         self.r = self.s = 0
+        entries = load_schedules() if schedule == "tuned" else \
+            ([] if schedule == "none" else list(schedule))
+        if entries:
+            self.set_schedule(entries)
+
+    def set_schedule(self, entries: list[dict]):
+        """nd_set_schedule with a list of {kind, r, s, n_r_max, peel_blocks}."""
+        tab = (Schedule * max(1, len(entries)))()
+        for i, e in enumerate(entries):
+            tab[i] = Schedule(int(e["r"]), int(e["s"]), int(e["n_r_max"]),
+                              int(e["peel_blocks"]), int(e.get("kind", ND_SCHED_SINGLE)))
+        self._check(self.lib.nd_set_schedule(self.h, tab, len(entries)))
 
     # -- error handling ----------------------------------------------------
     def _check(self, st: int):

@@ -16,7 +16,7 @@ import bench  # noqa: E402
 
 def _source_hash(kernel: str) -> str:
     src = os.path.join(ROOT, "paper_2306_08623_amd", "csrc")
-    first = {"k_peel": "nd_peel.hip", "k_count_s4": "nd_count.hip"}[kernel]
+    first = {"k_peel": "nd_peel_kern.h", "k_count_s4": "nd_count.hip"}[kernel]
     return hashlib.sha256(open(os.path.join(src, first), "rb").read() +
                           open(os.path.join(src, "nd_internal.h"), "rb").read()).hexdigest()
 

@@ -136,7 +136,7 @@ def test_batch_errors(ctx):
         ctx.decompose_batch([(ok, 2, 3), (bad, 2, 3)])
     assert e.value.code == nucleus.ND_E_BAD_GRAPH
     with pytest.raises(nucleus.NucleusError) as e:
-        ctx.decompose_batch([(ok, 2, 5)])
+        ctx.decompose_batch([(ok, 2, 8)])
     assert e.value.code == nucleus.ND_E_UNSUPPORTED
     with pytest.raises(nucleus.NucleusError) as e:
         ctx.decompose_batch([(ok, 3, 3)])

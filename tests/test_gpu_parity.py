@@ -105,6 +105,34 @@ def test_schedule_invariance(ctx):
                 assert np.array_equal(res.level.astype(np.uint64), d.level)
 
 
+def test_schedule_table(ctx):
+    """nd_set_schedule: a table that sends every (3,4) decomposition to a
+    grid of 8 workgroups gives the oracle's results (the grid changes no
+    result); malformed entries are refused."""
+    from paper_2306_08623_amd import nucleus
+    g = I.er_planted(800, 0.02, 10, 6, 20, 5)
+    tab = [{"kind": nucleus.ND_SCHED_SINGLE, "r": 3, "s": 4, "n_r_max": 10, "peel_blocks": 1024},
+           {"kind": nucleus.ND_SCHED_SINGLE, "r": 3, "s": 4, "n_r_max": (1 << 64) - 1,
+            "peel_blocks": 8},
+           {"kind": nucleus.ND_SCHED_BATCH, "r": 2, "s": 3, "n_r_max": (1 << 64) - 1,
+            "peel_blocks": 3}]
+    with nucleus.Context(device=0, schedule=tab) as c2:
+        check(c2, g, 3, 4, "schedule 8 blocks")
+        out = c2.decompose_batch([(I.er_planted(300, 0.03, 4, 5, 12, i), 2, 3) for i in range(6)])
+        for i, b in enumerate(out):
+            d = oracle.decompose(I.er_planted(300, 0.03, 4, 5, 12, i), 2, 3)
+            assert np.array_equal(b.coreness.astype(np.uint64), d.coreness), i
+            assert np.array_equal(b.parent, d.parent), i
+        for bad in ({"kind": 0, "r": 3, "s": 3, "n_r_max": 1, "peel_blocks": 1},
+                    {"kind": 0, "r": 1, "s": 9, "n_r_max": 1, "peel_blocks": 1},
+                    {"kind": 7, "r": 1, "s": 2, "n_r_max": 1, "peel_blocks": 1}):
+            with pytest.raises(nucleus.NucleusError) as e:
+                c2.set_schedule([bad])
+            assert e.value.code == nucleus.ND_E_INVALID_ARG
+        c2.set_schedule([])
+        check(c2, g, 3, 4, "schedule cleared")
+
+
 def test_error_paths(ctx):
     from paper_2306_08623_amd import nucleus
     bad = I.CSR(3, np.array([0, 1, 1, 1], dtype=np.uint64), np.array([1], dtype=np.uint32))
@@ -120,7 +148,7 @@ def test_error_paths(ctx):
         ctx.nd_set_rs(3, 3)
     assert e.value.code == nucleus.ND_E_INVALID_ARG
     with pytest.raises(nucleus.NucleusError) as e:
-        ctx.nd_set_rs(4, 6)
+        ctx.nd_set_rs(4, 8)
     assert e.value.code == nucleus.ND_E_UNSUPPORTED
     with nucleus.Context(device=0, mem_limit=4096) as small:
         with pytest.raises(nucleus.NucleusError) as e:

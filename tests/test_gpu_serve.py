@@ -127,7 +127,7 @@ def test_serve_errors():
     from paper_2306_08623_amd import nucleus
     with nucleus.Server(device=0) as srv:
         with pytest.raises(nucleus.NucleusError) as e:
-            srv.submit(I.complete(5), 2, 5)
+            srv.submit(I.complete(5), 2, 8)
         assert e.value.code == nucleus.ND_E_UNSUPPORTED
         bad = I.CSR(n=3, row_ptr=np.array([0, 1, 2, 2], np.uint64),
                     col=np.array([1, 3], np.uint32))

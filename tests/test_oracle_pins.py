@@ -60,6 +60,28 @@ def test_random_gnp_small(n, p, seed):
         _check_against_brute(g, r, s)
 
 
+GEN_PAIRS = [(r, s) for s in (5, 6, 7) for r in range(1, s)]
+
+
+@pytest.mark.parametrize("n,p,seed", [(8, 0.9, 21), (9, 0.88, 22), (11, 0.8, 24), (12, 0.78, 25),
+                                      (10, 0.95, 26)])
+def test_large_s_against_brute(n, p, seed):
+    """Every pair with s = 5..7 on dense small graphs (many 5-, 6- and
+    7-cliques, several core levels): counts, cores and trees equal brute
+    force."""
+    g = I.gnp(n, p, seed)
+    for r, s in GEN_PAIRS:
+        _check_against_brute(g, r, s)
+
+
+def test_large_s_planted():
+    """Two overlapping planted 7- and 8-cliques in a sparse graph: nested
+    nuclei at s = 5..7."""
+    g = I.er_planted(13, 0.2, 2, 7, 8, seed=31)
+    for r, s in GEN_PAIRS:
+        _check_against_brute(g, r, s)
+
+
 def test_planted_small():
     """A graph with overlapping planted cliques: deep, non-trivial trees."""
     g = I.er_planted(14, 0.15, 3, 4, 7, seed=9)
@@ -72,7 +94,8 @@ def test_planted_small():
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("n", range(1, 9))
-@pytest.mark.parametrize("r,s", [(1, 2), (1, 3), (2, 3), (1, 4), (2, 4), (3, 4), (2, 5), (3, 6)])
+@pytest.mark.parametrize("r,s", [(1, 2), (1, 3), (2, 3), (1, 4), (2, 4), (3, 4), (2, 5), (3, 6),
+                                 (1, 5), (4, 5), (5, 6), (1, 7), (4, 7), (6, 7)])
 def test_complete_graph(n, r, s):
     """K_n: n_r = C(n,r), n_s = C(n,s); every r-clique lies in C(n-r, s-r)
     s-cliques and has that core number; one node holds every r-clique."""
