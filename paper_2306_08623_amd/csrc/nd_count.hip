@@ -57,9 +57,9 @@ __global__ void __launch_bounds__(kCountBlock) k_count_s3(GraphView g, uint32_t 
   uint64_t local = 0;
   for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < g.m;
        j += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t u = segment_of(g.dgp, g.n, j);
     const uint32_t v = g.dgc[j];
     const uint32_t e_uv = g.dge[j];
+    const uint32_t u = g.eu[e_uv] ^ g.ev[e_uv] ^ v;   // the endpoint other than v
     uint64_t bu = g.dgp[u], eu = g.dgp[u + 1], bv = g.dgp[v], ev = g.dgp[v + 1];
     uint64_t lo = bv;
     for (uint64_t i = bu; i < eu && lo < ev; i++) {
@@ -119,11 +119,12 @@ __global__ void __launch_bounds__(kCountBlock) k_count_s4(GraphView g, uint32_t 
   uint64_t local = 0;
   const uint64_t nwaves = (uint64_t)gridDim.x * (kCountBlock / 64);
   for (uint64_t j = blockIdx.x * (uint64_t)(kCountBlock / 64) + wv; j < g.m; j += nwaves) {
-    const uint32_t u = segment_of(g.dgp, g.n, j);
-    const uint64_t bu = g.dgp[u], eu = g.dgp[u + 1];
-    if (kGlobal ? eu - bu <= light : eu - bu > cap) continue;   // the other kernel's edge
+    // the slot's source vertex: the endpoint of its edge other than v
     const uint32_t v = g.dgc[j];
     const uint32_t e_uv = g.dge[j];
+    const uint32_t u = g.eu[e_uv] ^ g.ev[e_uv] ^ v;
+    const uint64_t bu = g.dgp[u], eu = g.dgp[u + 1];
+    if (kGlobal ? eu - bu <= light : eu - bu > cap) continue;   // the other kernel's edge
     const uint64_t bv = g.dgp[v], ev = g.dgp[v + 1];
     // C2 = N+(u) intersect N+(v), ascending, with the edge ids to u and v
     uint32_t c = 0;
