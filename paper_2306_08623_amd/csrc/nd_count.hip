@@ -97,15 +97,16 @@ template <int R>
 constexpr uint32_t count_s4_arrays() { return R == 3 ? 4 : 3; }
 
 // kGlobal = false: the C2 arrays are in LDS (cap entries per wave) and the
-// kernel takes the edges u -> v whose u has out-degree <= cap; kGlobal =
-// true: they are in global memory (gbuf, one slice of cap entries per wave
-// of the grid) and the kernel takes the edges whose u has out-degree above
-// `light` (those the LDS kernel left; all of them when light = 0).
+// kernel takes the edges u -> v whose u has out-degree in (small, cap];
+// kGlobal = true: they are in global memory (gbuf, one slice of cap entries
+// per wave of the grid) and the kernel takes the edges whose u has
+// out-degree above `light` (those the LDS kernel left; all of them when
+// light = 0).
 template <int R, bool kGlobal>
 __global__ void __launch_bounds__(kCountBlock) k_count_s4(GraphView g, uint32_t *__restrict__ cnt,
                                                           DevScalars *sc, uint32_t cap,
                                                           uint32_t *__restrict__ gbuf,
-                                                          uint32_t light) {
+                                                          uint32_t light, uint32_t small) {
   extern __shared__ uint32_t s_c2[];
   const uint32_t wv = threadIdx.x / 64;
   const uint32_t lane = lane_id();
@@ -124,7 +125,9 @@ __global__ void __launch_bounds__(kCountBlock) k_count_s4(GraphView g, uint32_t 
     const uint32_t e_uv = g.dge[j];
     const uint32_t u = g.eu[e_uv] ^ g.ev[e_uv] ^ v;
     const uint64_t bu = g.dgp[u], eu = g.dgp[u + 1];
-    if (kGlobal ? eu - bu <= light : eu - bu > cap) continue;   // the other kernel's edge
+    // the other kernels' edges: rows up to `small` out-neighbours go to
+    // k_count_s4_small, rows above `light` to the global-memory variant
+    if (kGlobal ? eu - bu <= light : (eu - bu > cap || eu - bu <= small)) continue;
     const uint64_t bv = g.dgp[v], ev = g.dgp[v + 1];
     // C2 = N+(u) intersect N+(v), ascending, with the edge ids to u and v
     uint32_t c = 0;
@@ -232,6 +235,131 @@ __global__ void __launch_bounds__(kCountBlock) k_count_s4(GraphView g, uint32_t 
   if (lane == 0 && local) atomicAdd((unsigned long long *)&sc->n_s, (unsigned long long)local);
 }
 
+// Rows of small out-degree: a wave per edge would leave most lanes idle
+// (graphs of average degree 8 have out-degrees of a few), so groups of
+// kSmallG lanes take one edge u -> v each, for the edges whose u has
+// out-degree <= kSmallG: C2 in one ballot pass, its pairs over the group's
+// lanes, then the per-entry triangle counts. The wave's loop over its
+// groups' edges, and its barriers, stay wave-uniform; a group without an
+// edge in a pass has c = 0.
+constexpr uint32_t kSmallG = 16;
+
+template <int R>
+__global__ void __launch_bounds__(kCountBlock) k_count_s4_small(GraphView g,
+                                                                uint32_t *__restrict__ cnt,
+                                                                DevScalars *sc) {
+  constexpr uint32_t kGroups = 64 / kSmallG;
+  constexpr uint32_t A = count_s4_arrays<R>();
+  __shared__ uint32_t s_c2[(kCountBlock / 64) * kGroups * A * kSmallG];
+  const uint32_t wv = threadIdx.x / 64;
+  const uint32_t lane = lane_id();
+  const uint32_t gi = lane / kSmallG, gl = lane % kSmallG;
+  uint32_t *cv = s_c2 + ((uint64_t)wv * kGroups + gi) * A * kSmallG;
+  uint32_t *ceu = cv + kSmallG;
+  uint32_t *cev = ceu + kSmallG;
+  uint32_t *cn = cev + kSmallG;   // r = 3 only
+  uint64_t local = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * (kCountBlock / 64) * kGroups;
+  for (uint64_t jb = ((uint64_t)blockIdx.x * (kCountBlock / 64) + wv) * kGroups; jb < g.m;
+       jb += stride) {
+    const uint64_t j = jb + gi;
+    uint32_t u = 0, v = 0, e_uv = 0;
+    uint64_t bu = 0, deg = 0;
+    if (j < g.m) {
+      v = g.dgc[j];
+      e_uv = g.dge[j];
+      u = g.eu[e_uv] ^ g.ev[e_uv] ^ v;
+      bu = g.dgp[u];
+      deg = g.dgp[u + 1] - bu;
+      if (deg > kSmallG) deg = 0;   // left to the wave-per-edge kernel
+    }
+    // C2 = N+(u) intersect N+(v) in one pass of the group
+    bool hit = false;
+    uint32_t w = 0, e_uw = 0, e_vw = 0;
+    if (gl < deg) {
+      const uint64_t bv = g.dgp[v], ev = g.dgp[v + 1];
+      w = g.dgc[bu + gl];
+      const uint64_t p = find_u32<uint64_t>(g.dgc, bv, ev, w);
+      if (p < ev) {
+        hit = true;
+        e_uw = g.dge[bu + gl];
+        e_vw = g.dge[p];
+      }
+    }
+    const uint32_t gmask = (uint32_t)(ballot64(hit) >> (gi * kSmallG)) & ((1u << kSmallG) - 1);
+    const uint32_t c = __popc(gmask);
+    if (hit) {
+      const uint32_t slot = __popc(gmask & ((1u << gl) - 1));
+      cv[slot] = w;
+      ceu[slot] = e_uw;
+      cev[slot] = e_vw;
+      if (R == 3) cn[slot] = 0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // pairs {cv[a], cv[b]}, a < b, over the group's lanes in row-major order
+    const uint32_t npairs = c * (c - 1) / 2;
+    uint32_t a = 0, b = 1 + gl;
+    for (uint32_t q = gl; q < npairs; q += kSmallG, b += kSmallG) {
+      while (b >= c) {   // next row: row a + 1 starts at b = a + 2
+        const uint32_t over = b - c;
+        a++;
+        b = a + 1 + over;
+      }
+      const uint32_t x = cv[b];
+      const uint32_t wa = cv[a];
+      if (R == 3) {
+        // as in k_count_s4: x in W(u wa) iff wa and x are adjacent; the two
+        // slots name triangles {u, wa, x} and {v, wa, x}
+        const uint32_t euw = ceu[a], evw = cev[a];
+        const uint64_t b1 = g.wp[euw], f1 = g.wp[euw + 1], b2 = g.wp[evw], f2 = g.wp[evw + 1];
+        uint64_t p1, p2;
+        find2_u32<uint64_t>(g.wc, b1, f1, b2, f2, x, p1, p2);
+        if (p1 == f1) continue;
+        local++;
+        atomicAdd(&cn[a], 1u);
+        atomicAdd(&cn[b], 1u);
+        atomicAdd(&cnt[g.wt[p1]], 1u);
+        if (p2 == f2) atomicOr(&sc->status, ND_DERR_BADGRAPH);
+        else atomicAdd(&cnt[g.wt[p2]], 1u);
+        continue;
+      }
+      uint32_t lowv = wa, highv = x;
+      if (g.okey[x] < g.okey[wa]) { lowv = x; highv = wa; }
+      const uint64_t bl = g.dgp[lowv], el = g.dgp[lowv + 1];
+      const uint64_t p = find_u32<uint64_t>(g.dgc, bl, el, highv);
+      if (p == el) continue;
+      local++;
+      if (R == 1) {
+        atomicAdd(&cnt[u], 1u);
+        atomicAdd(&cnt[v], 1u);
+        atomicAdd(&cnt[wa], 1u);
+        atomicAdd(&cnt[x], 1u);
+      } else if (R == 2) {
+        const uint32_t e6[6] = {e_uv, ceu[a], cev[a], ceu[b], cev[b], g.dge[p]};
+        bool wrap = false;
+#pragma unroll
+        for (int z = 0; z < 6; z++) wrap |= atomicAdd(&cnt[e6[z]], 1u) == 0xFFFFFFFFu;
+        if (wrap) atomicOr(&sc->status, ND_DERR_OVERFLOW);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (R == 3 && gl < c && cn[gl] != 0) {
+      const uint32_t t = tri_lookup(g, u, v, cv[gl], e_uv, ceu[gl], cev[gl]);
+      if (t == ND_NONE) atomicOr(&sc->status, ND_DERR_BADGRAPH);
+      else atomicAdd(&cnt[t], cn[gl]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  local = wave_sum64(local);
+  if (lane == 0 && local) atomicAdd((unsigned long long *)&sc->n_s, (unsigned long long)local);
+}
+
 }  // namespace
 
 nd_status nd_stage_count(nd_ctx *c, const GraphView &g) {
@@ -288,9 +416,22 @@ nd_status nd_stage_count(nd_ctx *c, const GraphView &g) {
     // ND_FLAG_COUNT_GLOBAL) keep it in a global slice per wave
     const bool force_global = (c->flags & ND_FLAG_COUNT_GLOBAL) != 0;
     const uint32_t light = force_global ? 0u : std::min<uint32_t>(maxd, kC2Cap);
+    const uint32_t small = force_global ? 0u : kSmallG;
+    if (small) {
+      const uint32_t grid = nd_grid(g.m, (kCountBlock / 64) * (64 / kSmallG), 65536);
+      if (r == 1)
+        hipLaunchKernelGGL(k_count_s4_small<1>, dim3(grid), dim3(kCountBlock), 0, c->stream, g,
+                           cnt, sc);
+      else if (r == 2)
+        hipLaunchKernelGGL(k_count_s4_small<2>, dim3(grid), dim3(kCountBlock), 0, c->stream, g,
+                           cnt, sc);
+      else
+        hipLaunchKernelGGL(k_count_s4_small<3>, dim3(grid), dim3(kCountBlock), 0, c->stream, g,
+                           cnt, sc);
+    }
     const uint32_t arrays = r == 1 ? count_s4_arrays<1>()
                           : r == 2 ? count_s4_arrays<2>() : count_s4_arrays<3>();
-    if (light) {
+    if (light > small) {
       const uint32_t cap = std::max<uint32_t>(64, (light + 63) / 64 * 64);
       const uint32_t grid = nd_grid(g.m, kCountBlock / 64, 65536);
       const void *kern = r == 1 ? (const void *)k_count_s4<1, false>
@@ -302,13 +443,13 @@ nd_status nd_stage_count(nd_ctx *c, const GraphView &g) {
         return st;
       if (r == 1)
         hipLaunchKernelGGL((k_count_s4<1, false>), dim3(grid), dim3(kCountBlock), lds, c->stream,
-                           g, cnt, sc, cap, nullptr, 0u);
+                           g, cnt, sc, cap, nullptr, 0u, small);
       else if (r == 2)
         hipLaunchKernelGGL((k_count_s4<2, false>), dim3(grid), dim3(kCountBlock), lds, c->stream,
-                           g, cnt, sc, cap, nullptr, 0u);
+                           g, cnt, sc, cap, nullptr, 0u, small);
       else
         hipLaunchKernelGGL((k_count_s4<3, false>), dim3(grid), dim3(kCountBlock), lds, c->stream,
-                           g, cnt, sc, cap, nullptr, 0u);
+                           g, cnt, sc, cap, nullptr, 0u, small);
     }
     if (force_global || maxd > kC2Cap) {
       const uint32_t cap = std::max<uint32_t>(64, (maxd + 63) / 64 * 64);
@@ -321,13 +462,13 @@ nd_status nd_stage_count(nd_ctx *c, const GraphView &g) {
       const uint32_t grid = (uint32_t)(waves / (kCountBlock / 64));
       if (r == 1)
         hipLaunchKernelGGL((k_count_s4<1, true>), dim3(grid), dim3(kCountBlock), 0, c->stream, g,
-                           cnt, sc, cap, gbuf, light);
+                           cnt, sc, cap, gbuf, light, 0u);
       else if (r == 2)
         hipLaunchKernelGGL((k_count_s4<2, true>), dim3(grid), dim3(kCountBlock), 0, c->stream, g,
-                           cnt, sc, cap, gbuf, light);
+                           cnt, sc, cap, gbuf, light, 0u);
       else
         hipLaunchKernelGGL((k_count_s4<3, true>), dim3(grid), dim3(kCountBlock), 0, c->stream, g,
-                           cnt, sc, cap, gbuf, light);
+                           cnt, sc, cap, gbuf, light, 0u);
     }
   }
   st = nd_hip(c, hipGetLastError(), "count kernels");

@@ -327,37 +327,60 @@ __device__ __forceinline__ CommonScan common_scan(const uint64_t *rp, uint32_t u
   return c;
 }
 
+// Edge -> triangle lists, in groups of G lanes per edge: G = 64 for edges
+// whose shorter adjacency list has more than kEtlSmall entries, G = 16 for
+// the others (four edges per wave; sparse graphs have mostly short lists).
+// A group probes the shorter list G entries at a time and binary-searches
+// each entry in the longer one; hits are compacted in lane order, so W(e)
+// comes out ascending.
+constexpr uint32_t kEtlSmall = 32;
+constexpr uint32_t kEtlSmallG = 16;
+
+template <uint32_t G>
+__device__ __forceinline__ uint64_t group_bits(uint64_t mask, uint32_t gi) {
+  return G == 64 ? mask : (mask >> (gi * G)) & ((1ull << G) - 1);
+}
+
+template <uint32_t G>
+__device__ __forceinline__ bool etl_mine(const CommonScan &c) {
+  return G == 64 ? c.ae - c.as > kEtlSmall : c.ae - c.as <= kEtlSmall;
+}
+
+template <uint32_t G>
 __global__ void __launch_bounds__(kEtlBlock) k_etl_count(uint64_t m, const uint64_t *__restrict__ rp,
                                                          const uint32_t *__restrict__ col,
                                                          const uint32_t *__restrict__ eu,
                                                          const uint32_t *__restrict__ ev,
                                                          uint32_t *__restrict__ sup,
                                                          uint32_t *__restrict__ upc) {
-  const uint32_t lane = lane_id();
-  const uint64_t nwaves = (uint64_t)gridDim.x * (kEtlBlock / 64);
-  for (uint64_t e = blockIdx.x * (uint64_t)(kEtlBlock / 64) + threadIdx.x / 64; e < m;
-       e += nwaves) {
+  constexpr uint32_t kGroups = 64 / G;
+  const uint32_t lane = lane_id(), gi = lane / G, gl = lane % G;
+  const uint64_t ngroups = (uint64_t)gridDim.x * (kEtlBlock / 64) * kGroups;
+  for (uint64_t e = ((uint64_t)blockIdx.x * (kEtlBlock / 64) + threadIdx.x / 64) * kGroups + gi;
+       e < m; e += ngroups) {
     const uint32_t u = eu[e], v = ev[e];
     const CommonScan c = common_scan(rp, u, v);
+    if (!etl_mine<G>(c)) continue;
     uint32_t s = 0, up = 0;
-    for (uint64_t base = c.as; base < c.ae; base += 64) {
-      const uint64_t i = base + lane;
+    for (uint64_t base = c.as; base < c.ae; base += G) {
+      const uint64_t i = base + gl;
       bool hit = false, above = false;
       if (i < c.ae) {
         const uint32_t w = col[i];
         hit = find_u32<uint64_t>(col, c.bs, c.be, w) < c.be;
         above = hit && w > v;
       }
-      s += __popcll(ballot64(hit));
-      up += __popcll(ballot64(above));
+      s += __popcll(group_bits<G>(ballot64(hit), gi));
+      up += __popcll(group_bits<G>(ballot64(above), gi));
     }
-    if (lane == 0) {
+    if (gl == 0) {
       sup[e] = s;
       upc[e] = up;
     }
   }
 }
 
+template <uint32_t G>
 __global__ void __launch_bounds__(kEtlBlock) k_etl_fill(uint64_t m, const uint64_t *__restrict__ rp,
                                                         const uint32_t *__restrict__ col,
                                                         const uint32_t *__restrict__ eid,
@@ -370,17 +393,19 @@ __global__ void __launch_bounds__(kEtlBlock) k_etl_fill(uint64_t m, const uint64
                                                         uint32_t *__restrict__ wc,
                                                         uint32_t *__restrict__ wt,
                                                         uint32_t *__restrict__ te) {
-  const uint32_t lane = lane_id();
-  const uint64_t nwaves = (uint64_t)gridDim.x * (kEtlBlock / 64);
-  for (uint64_t e = blockIdx.x * (uint64_t)(kEtlBlock / 64) + threadIdx.x / 64; e < m;
-       e += nwaves) {
+  constexpr uint32_t kGroups = 64 / G;
+  const uint32_t lane = lane_id(), gi = lane / G, gl = lane % G;
+  const uint64_t ngroups = (uint64_t)gridDim.x * (kEtlBlock / 64) * kGroups;
+  for (uint64_t e = ((uint64_t)blockIdx.x * (kEtlBlock / 64) + threadIdx.x / 64) * kGroups + gi;
+       e < m; e += ngroups) {
     const uint32_t u = eu[e], v = ev[e];
     const CommonScan c = common_scan(rp, u, v);
+    if (!etl_mine<G>(c)) continue;
     uint64_t o = wp[e];
     const uint64_t first_up = wp[e] + (sup[e] - upc[e]);
     const uint64_t tb = trib[e];
-    for (uint64_t base = c.as; base < c.ae; base += 64) {
-      const uint64_t i = base + lane;
+    for (uint64_t base = c.as; base < c.ae; base += G) {
+      const uint64_t i = base + gl;
       bool hit = false;
       uint32_t w = 0;
       uint64_t p = 0;
@@ -389,9 +414,9 @@ __global__ void __launch_bounds__(kEtlBlock) k_etl_fill(uint64_t m, const uint64
         p = find_u32<uint64_t>(col, c.bs, c.be, w);
         hit = p < c.be;
       }
-      const uint64_t mask = ballot64(hit);
+      const uint64_t mask = group_bits<G>(ballot64(hit), gi);
       if (hit) {
-        const uint64_t below = mask & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)));
+        const uint64_t below = mask & ((1ull << gl) - 1);
         const uint64_t slot = o + __popcll(below);
         const uint64_t su = c.u_short ? i : p, sv = c.u_short ? p : i;   // w's slots in N(u), N(v)
         wc[slot] = w;
@@ -765,7 +790,10 @@ nd_status nd_stage_prep(nd_ctx *c, GraphView *gv) {
     if (!wp) return st;
     uint64_t *trib = (uint64_t *)nd_buf(c, B_TRIB, (m + 1) * 8, &st);
     if (!trib) return st;
-    hipLaunchKernelGGL(k_etl_count, dim3(nd_grid(m, kEtlBlock / 64, 65536)), dim3(kEtlBlock), 0,
+    hipLaunchKernelGGL(k_etl_count<kEtlSmallG>,
+                       dim3(nd_grid(m, (kEtlBlock / 64) * (64 / kEtlSmallG), 65536)),
+                       dim3(kEtlBlock), 0, c->stream, m, rp, col, eu, ev, sup, upc);
+    hipLaunchKernelGGL(k_etl_count<64>, dim3(nd_grid(m, kEtlBlock / 64, 65536)), dim3(kEtlBlock), 0,
                        c->stream, m, rp, col, eu, ev, sup, upc);
     uint64_t nw = 0, ntri = 0;
     st = nd_exclusive_scan_u32_to_u64(c, sup, wp, m, &nw);
@@ -782,8 +810,12 @@ nd_status nd_stage_prep(nd_ctx *c, GraphView *gv) {
     uint32_t *te = (uint32_t *)nd_buf(c, B_TE, std::max<uint64_t>(3 * ntri, 1) * 4, &st);
     if (!te) return st;
     if (nw) {
-      hipLaunchKernelGGL(k_etl_fill, dim3(nd_grid(m, kEtlBlock / 64, 65536)), dim3(kEtlBlock), 0,
-                         c->stream, m, rp, col, eid, eu, ev, sup, upc, wp, trib, wc, wt, te);
+      hipLaunchKernelGGL(k_etl_fill<kEtlSmallG>,
+                         dim3(nd_grid(m, (kEtlBlock / 64) * (64 / kEtlSmallG), 65536)),
+                         dim3(kEtlBlock), 0, c->stream, m, rp, col, eid, eu, ev, sup, upc, wp,
+                         trib, wc, wt, te);
+      hipLaunchKernelGGL(k_etl_fill<64>, dim3(nd_grid(m, kEtlBlock / 64, 65536)), dim3(kEtlBlock),
+                         0, c->stream, m, rp, col, eid, eu, ev, sup, upc, wp, trib, wc, wt, te);
       hipLaunchKernelGGL(k_etl_resolve, dim3(nd_grid(nw, 256, 65536)), dim3(256), 0, c->stream, m,
                          nw, ev, wp, wc, wt, &sc->status);
     }
