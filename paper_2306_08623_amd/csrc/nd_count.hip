@@ -93,6 +93,23 @@ __global__ void k_count_inc(uint64_t nr, const uint64_t *__restrict__ io, uint32
     cnt[x] = (uint32_t)(io[x + 1] - io[x]);
 }
 
+// one 4-clique's increments of its six edges' counts; with kWrap, a count
+// that wraps past 2^32 - 1 sets ND_DERR_OVERFLOW (returning atomics, which
+// wait for their result: only used when the bound allows a wrap)
+template <bool kWrap>
+__device__ __forceinline__ void count_edges6(uint32_t *cnt, const uint32_t (&e6)[6],
+                                             DevScalars *sc) {
+  if (kWrap) {
+    bool wrap = false;
+#pragma unroll
+    for (int z = 0; z < 6; z++) wrap |= atomicAdd(&cnt[e6[z]], 1u) == 0xFFFFFFFFu;
+    if (wrap) atomicOr(&sc->status, ND_DERR_OVERFLOW);
+  } else {
+#pragma unroll
+    for (int z = 0; z < 6; z++) atomicAdd(&cnt[e6[z]], 1u);
+  }
+}
+
 template <int R>
 constexpr uint32_t count_s4_arrays() { return R == 3 ? 4 : 3; }
 
@@ -102,7 +119,7 @@ constexpr uint32_t count_s4_arrays() { return R == 3 ? 4 : 3; }
 // per wave of the grid) and the kernel takes the edges whose u has
 // out-degree above `light` (those the LDS kernel left; all of them when
 // light = 0).
-template <int R, bool kGlobal>
+template <int R, bool kGlobal, bool kWrap>
 __global__ void __launch_bounds__(kCountBlock) k_count_s4(GraphView g, uint32_t *__restrict__ cnt,
                                                           DevScalars *sc, uint32_t cap,
                                                           uint32_t *__restrict__ gbuf,
@@ -209,13 +226,11 @@ __global__ void __launch_bounds__(kCountBlock) k_count_s4(GraphView g, uint32_t 
         atomicAdd(&cnt[w], 1u);
         atomicAdd(&cnt[x], 1u);
       } else if (R == 2) {
-        // (2,4): an edge's count is at most C(|common neighbours|, 2), which
-        // can pass 2^32: a wrap is caught where it happens
+        // (2,4): an edge's count is at most C(|common neighbours|, 2); when
+        // that can pass 2^32 (kWrap) a wrap is caught where it happens, else
+        // the increments need no result
         const uint32_t e6[6] = {e_uv, ceu[a], cev[a], ceu[b], cev[b], g.dge[p]};
-        bool wrap = false;
-#pragma unroll
-        for (int z = 0; z < 6; z++) wrap |= atomicAdd(&cnt[e6[z]], 1u) == 0xFFFFFFFFu;
-        if (wrap) atomicOr(&sc->status, ND_DERR_OVERFLOW);
+        count_edges6<kWrap>(cnt, e6, sc);
       }
     }
     if (R == 3) {
@@ -244,7 +259,7 @@ __global__ void __launch_bounds__(kCountBlock) k_count_s4(GraphView g, uint32_t 
 // edge in a pass has c = 0.
 constexpr uint32_t kSmallG = 16;
 
-template <int R>
+template <int R, bool kWrap>
 __global__ void __launch_bounds__(kCountBlock) k_count_s4_small(GraphView g,
                                                                 uint32_t *__restrict__ cnt,
                                                                 DevScalars *sc) {
@@ -338,10 +353,7 @@ __global__ void __launch_bounds__(kCountBlock) k_count_s4_small(GraphView g,
         atomicAdd(&cnt[x], 1u);
       } else if (R == 2) {
         const uint32_t e6[6] = {e_uv, ceu[a], cev[a], ceu[b], cev[b], g.dge[p]};
-        bool wrap = false;
-#pragma unroll
-        for (int z = 0; z < 6; z++) wrap |= atomicAdd(&cnt[e6[z]], 1u) == 0xFFFFFFFFu;
-        if (wrap) atomicOr(&sc->status, ND_DERR_OVERFLOW);
+        count_edges6<kWrap>(cnt, e6, sc);
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -358,6 +370,48 @@ __global__ void __launch_bounds__(kCountBlock) k_count_s4_small(GraphView g,
   }
   local = wave_sum64(local);
   if (lane == 0 && local) atomicAdd((unsigned long long *)&sc->n_s, (unsigned long long)local);
+}
+
+// The three 4-clique kernels of one r: rows of at most kSmallG
+// out-neighbours in 16-lane groups, rows up to kC2Cap with C2 on chip, heavier
+// rows (a graph of degeneracy above kC2Cap, or every row with
+// ND_FLAG_COUNT_GLOBAL) with C2 in a global slice per wave.
+template <int R, bool kWrap>
+nd_status launch_count_s4(nd_ctx *c, const GraphView &g, uint32_t *cnt, DevScalars *sc,
+                          uint32_t maxd, bool force_global) {
+  nd_status st;
+  const uint32_t light = force_global ? 0u : std::min<uint32_t>(maxd, kC2Cap);
+  const uint32_t small = force_global ? 0u : kSmallG;
+  constexpr uint32_t arrays = count_s4_arrays<R>();
+  if (small) {
+    const uint32_t grid = nd_grid(g.m, (kCountBlock / 64) * (64 / kSmallG), 65536);
+    hipLaunchKernelGGL((k_count_s4_small<R, kWrap>), dim3(grid), dim3(kCountBlock), 0, c->stream,
+                       g, cnt, sc);
+  }
+  if (light > small) {
+    const uint32_t cap = std::max<uint32_t>(64, (light + 63) / 64 * 64);
+    const uint32_t grid = nd_grid(g.m, kCountBlock / 64, 65536);
+    const size_t lds = (size_t)(kCountBlock / 64) * arrays * cap * 4;
+    if ((st = nd_hip(c, hipFuncSetAttribute((const void *)k_count_s4<R, false, kWrap>,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+                     "count LDS size")) != ND_OK)
+      return st;
+    hipLaunchKernelGGL((k_count_s4<R, false, kWrap>), dim3(grid), dim3(kCountBlock), lds,
+                       c->stream, g, cnt, sc, cap, nullptr, 0u, small);
+  }
+  if (force_global || maxd > kC2Cap) {
+    const uint32_t cap = std::max<uint32_t>(64, (maxd + 63) / 64 * 64);
+    // waves of the global kernel: as many as 1 GiB of C2 slices holds,
+    // between 64 and 65,536
+    const uint64_t per_wave = (uint64_t)arrays * cap * 4;
+    const uint64_t waves = std::max<uint64_t>(64, std::min<uint64_t>(65536, (1ull << 30) / per_wave));
+    uint32_t *gbuf = (uint32_t *)nd_buf(c, B_C2G, waves * per_wave, &st);
+    if (!gbuf) return st;
+    const uint32_t grid = (uint32_t)(waves / (kCountBlock / 64));
+    hipLaunchKernelGGL((k_count_s4<R, true, kWrap>), dim3(grid), dim3(kCountBlock), 0, c->stream,
+                       g, cnt, sc, cap, gbuf, light, 0u);
+  }
+  return ND_OK;
 }
 
 }  // namespace
@@ -404,72 +458,28 @@ nd_status nd_stage_count(nd_ctx *c, const GraphView &g) {
       hipLaunchKernelGGL(k_count_s3<2>, dim3(grid), dim3(kCountBlock), 0, c->stream, g, cnt, sc);
   } else if (s == 4 && g.m) {
     // C2 (common out-neighbours of an edge) has at most max-out-degree
-    // entries: the LDS arrays are sized to it, so that more workgroups fit
-    uint32_t maxd = 0;
+    // entries: the LDS arrays are sized to it, so that more workgroups fit;
+    // (2,4) also reads the largest triangle count of an edge, which bounds
+    // its counts by C(t, 2)
+    uint32_t maxd = 0, maxsup = 0;
     if ((st = nd_hip(c, hipMemcpyAsync(&maxd, &sc->max_outdeg, 4, hipMemcpyDeviceToHost,
                                        c->stream), "max out-degree")) != ND_OK ||
+        (st = nd_hip(c, hipMemcpyAsync(&maxsup, &sc->max_sup, 4, hipMemcpyDeviceToHost,
+                                       c->stream), "max support")) != ND_OK ||
         (st = nd_hip(c, hipStreamSynchronize(c->stream), "max out-degree")) != ND_OK)
       return st;
     c->info.max_outdeg = maxd;
-    // rows of out-degree up to kC2Cap keep C2 on chip; heavier rows (a
-    // graph of degeneracy above kC2Cap, or every row with
-    // ND_FLAG_COUNT_GLOBAL) keep it in a global slice per wave
     const bool force_global = (c->flags & ND_FLAG_COUNT_GLOBAL) != 0;
-    const uint32_t light = force_global ? 0u : std::min<uint32_t>(maxd, kC2Cap);
-    const uint32_t small = force_global ? 0u : kSmallG;
-    if (small) {
-      const uint32_t grid = nd_grid(g.m, (kCountBlock / 64) * (64 / kSmallG), 65536);
-      if (r == 1)
-        hipLaunchKernelGGL(k_count_s4_small<1>, dim3(grid), dim3(kCountBlock), 0, c->stream, g,
-                           cnt, sc);
-      else if (r == 2)
-        hipLaunchKernelGGL(k_count_s4_small<2>, dim3(grid), dim3(kCountBlock), 0, c->stream, g,
-                           cnt, sc);
-      else
-        hipLaunchKernelGGL(k_count_s4_small<3>, dim3(grid), dim3(kCountBlock), 0, c->stream, g,
-                           cnt, sc);
+    if (r == 1) {
+      st = launch_count_s4<1, false>(c, g, cnt, sc, maxd, force_global);
+    } else if (r == 2) {
+      const bool wrap = (uint64_t)maxsup * (maxsup - (maxsup ? 1 : 0)) / 2 > 0xFFFFFFFFull;
+      st = wrap ? launch_count_s4<2, true>(c, g, cnt, sc, maxd, force_global)
+                : launch_count_s4<2, false>(c, g, cnt, sc, maxd, force_global);
+    } else {
+      st = launch_count_s4<3, false>(c, g, cnt, sc, maxd, force_global);
     }
-    const uint32_t arrays = r == 1 ? count_s4_arrays<1>()
-                          : r == 2 ? count_s4_arrays<2>() : count_s4_arrays<3>();
-    if (light > small) {
-      const uint32_t cap = std::max<uint32_t>(64, (light + 63) / 64 * 64);
-      const uint32_t grid = nd_grid(g.m, kCountBlock / 64, 65536);
-      const void *kern = r == 1 ? (const void *)k_count_s4<1, false>
-                       : r == 2 ? (const void *)k_count_s4<2, false>
-                                : (const void *)k_count_s4<3, false>;
-      const size_t lds = (size_t)(kCountBlock / 64) * arrays * cap * 4;
-      if ((st = nd_hip(c, hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                              (int)lds), "count LDS size")) != ND_OK)
-        return st;
-      if (r == 1)
-        hipLaunchKernelGGL((k_count_s4<1, false>), dim3(grid), dim3(kCountBlock), lds, c->stream,
-                           g, cnt, sc, cap, nullptr, 0u, small);
-      else if (r == 2)
-        hipLaunchKernelGGL((k_count_s4<2, false>), dim3(grid), dim3(kCountBlock), lds, c->stream,
-                           g, cnt, sc, cap, nullptr, 0u, small);
-      else
-        hipLaunchKernelGGL((k_count_s4<3, false>), dim3(grid), dim3(kCountBlock), lds, c->stream,
-                           g, cnt, sc, cap, nullptr, 0u, small);
-    }
-    if (force_global || maxd > kC2Cap) {
-      const uint32_t cap = std::max<uint32_t>(64, (maxd + 63) / 64 * 64);
-      // waves of the global kernel: as many as 1 GiB of C2 slices holds,
-      // between 64 and 65,536
-      const uint64_t per_wave = (uint64_t)arrays * cap * 4;
-      const uint64_t waves = std::max<uint64_t>(64, std::min<uint64_t>(65536, (1ull << 30) / per_wave));
-      uint32_t *gbuf = (uint32_t *)nd_buf(c, B_C2G, waves * per_wave, &st);
-      if (!gbuf) return st;
-      const uint32_t grid = (uint32_t)(waves / (kCountBlock / 64));
-      if (r == 1)
-        hipLaunchKernelGGL((k_count_s4<1, true>), dim3(grid), dim3(kCountBlock), 0, c->stream, g,
-                           cnt, sc, cap, gbuf, light, 0u);
-      else if (r == 2)
-        hipLaunchKernelGGL((k_count_s4<2, true>), dim3(grid), dim3(kCountBlock), 0, c->stream, g,
-                           cnt, sc, cap, gbuf, light, 0u);
-      else
-        hipLaunchKernelGGL((k_count_s4<3, true>), dim3(grid), dim3(kCountBlock), 0, c->stream, g,
-                           cnt, sc, cap, gbuf, light, 0u);
-    }
+    if (st != ND_OK) return st;
   }
   st = nd_hip(c, hipGetLastError(), "count kernels");
   if (c->events_ok) (void)hipEventRecord(c->ev[8], c->stream);

@@ -445,7 +445,8 @@ struct DevScalars {
   uint32_t max_outdeg;
   uint32_t orient_round;
   uint32_t n_kept;         // tree: kept nodes
-  uint32_t pad[5];
+  uint32_t max_sup;        // (2,4): largest number of triangles on one edge
+  uint32_t pad[4];
   alignas(128) uint64_t bar[kBarWords];   // grid barrier state (zeroed before each launch)
 };
 

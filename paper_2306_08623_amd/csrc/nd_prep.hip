@@ -795,6 +795,9 @@ nd_status nd_stage_prep(nd_ctx *c, GraphView *gv) {
                        dim3(kEtlBlock), 0, c->stream, m, rp, col, eu, ev, sup, upc);
     hipLaunchKernelGGL(k_etl_count<64>, dim3(nd_grid(m, kEtlBlock / 64, 65536)), dim3(kEtlBlock), 0,
                        c->stream, m, rp, col, eu, ev, sup, upc);
+    if (c->r == 2 && c->s == 4)   // bounds the (2,4) counts: C(triangles on the edge, 2)
+      hipLaunchKernelGGL(k_max_u32, dim3(nd_grid(m, 256, 4096)), dim3(256), 0, c->stream, sup, m,
+                         &sc->max_sup);
     uint64_t nw = 0, ntri = 0;
     st = nd_exclusive_scan_u32_to_u64(c, sup, wp, m, &nw);
     if (st != ND_OK) return st;
