@@ -5,12 +5,14 @@ factor 16, seed 2), in the launch configuration the benchmark times.
 * (2,3): the oracle's full results were hashed once by
   tests/golden/make_golden.py (about 9 minutes on one core); the GPU outputs
   must hash identically.
-* (3,4): a full oracle run would take hours. The r-clique listing is compared
-  in full against the oracle's own listing; counts and core numbers are
-  checked on 20,000 sampled triangles against values the oracle computes one
-  triangle at a time, with the certificates of tests/certify.py; the tree is
-  checked for the properties that hold at any size, for adjacency closure on
-  sampled triangles and for connectivity of sampled small nodes.
+* (3,4): the oracle's full results, hashed once by make_golden.py (hours on
+  one core), must hash identically. Independently of that file, the
+  r-clique listing is compared in full against the oracle's own listing;
+  counts and core numbers are checked on 20,000 sampled triangles against
+  values the oracle computes one triangle at a time, with the certificates
+  of tests/certify.py; the tree is checked for the properties that hold at
+  any size, for adjacency closure on sampled triangles and for
+  connectivity of sampled small nodes.
 """
 from __future__ import annotations
 
@@ -69,6 +71,26 @@ def test_rmat18_23_golden(ctx, rmat18):
     assert gold["csr_sha256"] == rmat18.sha256()
     _say("[fullsize] rmat18 (2,3) vs the oracle's hashed results")
     res = ctx.decompose(rmat18, 2, 3)
+    info = res.info
+    assert (info["n_r"], info["n_s"], info["k"], info["n_int"]) == \
+        (gold["n_r"], gold["n_s"], gold["k"], gold["n_int"])
+    got = result_hashes(res.rcliques, res.counts, res.coreness, res.parent, res.level)
+    assert got == gold["sha256"]
+
+
+@pytest.mark.timeout(300)
+def test_rmat18_34_golden(ctx, rmat18):
+    """(3,4) on R-MAT 18, bit-exact: every output hashes to the full oracle
+    run's values (tests/golden/rmat18_34.json, written by make_golden.py)."""
+    from make_golden import result_hashes
+    path = os.path.join(HERE, "golden", "rmat18_34.json")
+    if not os.path.exists(path):
+        pytest.skip("the oracle's R-MAT 18 (3,4) golden has not been written")
+    with open(path) as f:
+        gold = json.load(f)
+    assert gold["csr_sha256"] == rmat18.sha256()
+    _say("[fullsize] rmat18 (3,4) vs the oracle's hashed results")
+    res = ctx.decompose(rmat18, 3, 4)
     info = res.info
     assert (info["n_r"], info["n_s"], info["k"], info["n_int"]) == \
         (gold["n_r"], gold["n_s"], gold["k"], gold["n_int"])
