@@ -1227,19 +1227,33 @@ struct HierArgs {
   uint32_t *progress;
 };
 
-__device__ __forceinline__ void hier_pair(const HierArgs &a, uint32_t R, uint32_t R2, uint32_t c,
-                                          uint64_t &unites, uint32_t *retries) {
+// rootR: a root R had during this visit. Sets only grow, so finding the
+// partner side at rootR proves both are joined already; a rootR that has
+// since lost its root status only sends the pair down the full path.
+__device__ __forceinline__ void hier_pair(const HierArgs &a, uint32_t R, uint32_t rootR,
+                                          uint32_t R2, uint32_t c, uint64_t &unites,
+                                          uint32_t *retries) {
+  // Every uf union is paired with a tuf union of the same two sets (or of
+  // sets containing them), so a uf set always lies inside one tuf set once
+  // the level's unions are done: when the uf union finds both sides already
+  // joined, the tuf union would join nothing either and is skipped.
   const uint32_t n2 = a.nd[R2];
   if (n2 == c) {   // same core: one component, one tree
-    unites += uf_unite(a.uf, R, R2, retries) != ND_NONE;
-    uf_unite(a.tuf, R, R2, retries);
+    if (uf_find(a.uf, R2) == rootR) return;
+    if (uf_unite(a.uf, R, R2, retries) != ND_NONE) {
+      unites++;
+      uf_unite(a.tuf, R, R2, retries);
+    }
     return;
   }
   const uint32_t T = uf_find(a.tuf, R2);
   const uint32_t B = ld_acq32(&a.bottom[T]);
   if (a.nd[B] == c) {   // R2's tree already hangs below a core-c component
-    unites += uf_unite(a.uf, B, R, retries) != ND_NONE;
-    uf_unite(a.tuf, T, R, retries);
+    if (uf_find(a.uf, B) == rootR) return;
+    if (uf_unite(a.uf, B, R, retries) != ND_NONE) {
+      unites++;
+      uf_unite(a.tuf, T, R, retries);
+    }
     return;
   }
   // R2's tree still ends at a component of a higher core: hang it below R
@@ -1349,11 +1363,12 @@ __global__ void __launch_bounds__(kPeelBlock) k_hier(HierArgs a) {
         uint32_t others[NO];
         if (Sh::visit(g, R, (uint32_t)(qoff - before), others)) {
           visits++;
+          const uint32_t rootR = uf_find(a.uf, R);
 #pragma unroll
           for (int j = 0; j < NO; j++) {
             if (a.nd[others[j]] >= c) {
               pairs++;
-              hier_pair(a, R, others[j], c, unites, retries);
+              hier_pair(a, R, rootR, others[j], c, unites, retries);
             }
           }
         }
