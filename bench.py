@@ -53,6 +53,21 @@ PEEL_BYTES_PER_VISIT = {(1, 2): 16, (2, 3): 32, (3, 4): 60, (2, 4): 80, (1, 3): 
 PEEL_BYTES_PER_RCLIQUE = {(1, 2): 20, (2, 3): 24, (3, 4): 28, (2, 4): 28, (1, 3): 20, (1, 4): 20}
 COUNT_BYTES_PER_SCLIQUE = {(1, 2): 0, (2, 3): 36, (3, 4): 64, (2, 4): 72, (1, 3): 36, (1, 4): 48}
 
+
+def byte_model(r: int, s: int) -> tuple[int, int, int]:
+    """(peel bytes per visit, per peeled r-clique, count bytes per s-clique).
+    s = 5..7 keep their s-cliques: a visit reads its incidence entry (4 B)
+    and the s-clique's C(s,r) r-clique ids (4 B each), then touches the
+    C(s,r) - 1 others' state (12 B each); a peeled r-clique also reads its
+    two incidence offsets (8 B more); counting writes the ids and the
+    incidence entry of every (r-clique, s-clique) pair and increments its
+    count (16 B per pair)."""
+    if (r, s) in PEEL_BYTES_PER_VISIT:
+        return PEEL_BYTES_PER_VISIT[(r, s)], PEEL_BYTES_PER_RCLIQUE[(r, s)], \
+            COUNT_BYTES_PER_SCLIQUE[(r, s)]
+    c = comb(s, r)
+    return 4 + 4 * c + 12 * (c - 1), 36, 16 * c
+
 DESCS = {
     "chunglu4m": "Chung-Lu n=4,000,000, exponent 2.1, ~40M edges, max expected degree 20,000, "
                  "+ 1,000 communities of size 20..200 at density 0.6, seed 3",
@@ -441,9 +456,9 @@ def measure(name: str, r: int, s: int, steps: int, warmup: int, peel_blocks: int
     # library's stream around each launch
     peel_ms = sum(i["ms_peel_kernel"] for i in infos) / len(infos)
     count_ms = sum(i["ms_count_kernel"] for i in infos) / len(infos)
-    peel_bytes = (PEEL_BYTES_PER_VISIT[(r, s)] * info["visits"]
-                  + PEEL_BYTES_PER_RCLIQUE[(r, s)] * info["n_r"])
-    count_bytes = COUNT_BYTES_PER_SCLIQUE[(r, s)] * n_s
+    b_visit, b_rclique, b_sclique = byte_model(r, s)
+    peel_bytes = b_visit * info["visits"] + b_rclique * info["n_r"]
+    count_bytes = b_sclique * n_s
     if peel_ms >= count_ms:
         kname, kms, kbytes = "k_peel", peel_ms, peel_bytes
     else:
