@@ -564,7 +564,7 @@ def main() -> int:
     ap.add_argument("--secondary", default="rmat18",
                     help="a second workload measured the same way ('' to skip)")
     ap.add_argument("--secondary-steps", type=int, default=3)
-    ap.add_argument("--cpu-scale", type=int, default=8,
+    ap.add_argument("--cpu-scale", type=int, default=7,
                     help="the oracle baseline runs on the workload's generator at a size "
                          "reduced by 2^scale (R-MAT: scale lower by this much) (0: skip)")
     ap.add_argument("--peel-blocks", type=int, default=0)
