@@ -137,6 +137,35 @@ def test_rmat18_34_sampled(ctx, rmat18):
 
 
 @pytest.mark.timeout(300)
+def test_rmat18_34_el_equals_te(rmat18):
+    """(3,4) at full size, the hierarchy built two independent ways: during
+    the peel (Algorithm 5) and by the descending-core pass after it. Core
+    numbers, counts and the canonical trees must be identical element by
+    element (the two share only the peel's core numbers and the tree
+    stage), and every r-clique sits in the node of its own level or is a
+    root leaf of core 0."""
+    from paper_2306_08623_amd import nucleus
+    out = {}
+    for mode in ("el", "te"):
+        _say(f"[fullsize] rmat18 (3,4) hierarchy {mode}")
+        with nucleus.Context(device=0, hierarchy=mode) as c2:
+            out[mode] = c2.decompose(rmat18, 3, 4)
+    el, te = out["el"], out["te"]
+    assert el.info["hier_te"] == 0 and te.info["hier_te"] == 1
+    for f in ("counts", "coreness", "parent", "level"):
+        assert np.array_equal(getattr(el, f), getattr(te, f)), f
+    n_r = el.coreness.size
+    par = el.parent[:n_r]
+    core = el.coreness.astype(np.int64)
+    inner = par != np.iinfo(np.uint64).max
+    # an r-clique of core c >= 1 shares an s-clique with r-cliques of core
+    # >= c, so the smallest node holding it is the node of level c
+    assert np.array_equal(inner, core > 0)
+    lv = el.level.astype(np.int64)[(par[inner] - n_r).astype(np.int64)]
+    assert np.array_equal(lv, core[inner])
+
+
+@pytest.mark.timeout(300)
 def test_rmat18_23_approx_bound(ctx, rmat18):
     """Algorithm 2 at full size: the GPU's exact (2,3) core numbers hash to
     the oracle's golden values; the approximate ones, for three deltas, lie
