@@ -37,9 +37,9 @@ def cl4m():
     return I.workload_chung_lu_4m()
 
 
-def _run(g, r, s):
+def _run(g, r, s, hierarchy="auto"):
     from paper_2306_08623_amd import nucleus
-    with nucleus.Context(device=0, progress=True) as ctx:
+    with nucleus.Context(device=0, progress=True, hierarchy=hierarchy) as ctx:
         ctx.load_csr(g)
         ctx.nd_set_rs(r, s)
         ctx.nd_decompose()
@@ -87,6 +87,14 @@ def _check(g, r, s, res, n_sample):
 def test_chunglu4m_34(cl4m):
     _say("[cl4m] (3,4): GPU decomposition")
     res = _run(cl4m, 3, 4)
+    # the hierarchy built after the peel instead of during it: identical
+    # results, element by element
+    _say("[cl4m] (3,4): GPU decomposition, descending-core hierarchy")
+    te = _run(cl4m, 3, 4, hierarchy="te")
+    assert res["info"]["hier_te"] == 0 and te["info"]["hier_te"] == 1
+    for f in ("counts", "core", "parent", "level"):
+        assert np.array_equal(res[f], te[f]), f
+    del te
     _check(cl4m, 3, 4, res, 3000)
 
 
