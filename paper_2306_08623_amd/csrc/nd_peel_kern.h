@@ -41,6 +41,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstring>
+#include <type_traits>
 
 // Arguments of the persistent peel kernel (one definition for every file
 // that includes this header).
@@ -52,6 +53,7 @@ struct PeelArgs {
   uint8_t *pst;       // peel state: kAlive, kPeeledNow (this round), kPeeledBefore
   uint32_t *uf;       // union-find parent
   uint32_t *L;        // nearest lower core link of a uf root
+  uint64_t *frec;     // (3,4): per frontier slot, 32 B of list ranges (Shape::len_rec)
   uint32_t *F0, *F1;  // frontiers by round parity
   uint64_t *wscan;    // per frontier slot: inclusive work prefix in its segment
   uint32_t *al0, *al1;  // remaining r-cliques by scan parity, one segment per block
@@ -410,6 +412,14 @@ __device__ __forceinline__ uint64_t gallop_u64(const uint64_t *a, uint64_t lo, u
 template <int R_, int S_>
 struct Shape;
 
+// Shapes with kRec = true have the mark pass store, per frontier slot, what
+// their visits need of the r-clique (len_rec), and visit from that record
+// (visit_rec) instead of re-reading the r-clique's tables on every probe.
+template <class S, class = void>
+struct RecOf : std::false_type {};
+template <class S>
+struct RecOf<S, std::void_t<decltype(S::kRec)>> : std::integral_constant<bool, S::kRec> {};
+
 // (1,2): R = vertex v; every neighbour x closes an s-clique {v, x}.
 template <>
 struct Shape<1, 2> {
@@ -538,6 +548,45 @@ struct Shape<1, 4> {
 template <>
 struct Shape<3, 4> {
   static constexpr int kOthers = 3;
+  static constexpr bool kRec = true;
+  // record: the start of the shortest of the three W lists, the starts of
+  // the other two, and their two lengths (32 B); a probe then needs one
+  // record read before its list entry instead of the triangle's edge ids
+  // and six W offsets
+  __device__ static uint32_t len_rec(const GraphView &g, uint32_t R, uint64_t *rec) {
+    const uint32_t e0 = g.te[3ull * R], e1 = g.te[3ull * R + 1], e2 = g.te[3ull * R + 2];
+    uint64_t b0 = g.wp[e0], f0 = g.wp[e0 + 1], b1 = g.wp[e1], f1 = g.wp[e1 + 1],
+             b2 = g.wp[e2], f2 = g.wp[e2 + 1];
+    const uint64_t s0 = f0 - b0, s1 = f1 - b1, s2 = f2 - b2;
+    // the same choice of the probed list as visit() below
+    if (s1 < s0 && s1 <= s2) {
+      uint64_t t = b0; b0 = b1; b1 = t;
+      t = f0; f0 = f1; f1 = t;
+    } else if (s2 < s0 && s2 < s1) {
+      uint64_t t = b0; b0 = b2; b2 = t;
+      t = f0; f0 = f2; f2 = t;
+    }
+    rec[0] = b0;
+    rec[1] = b1;
+    rec[2] = b2;
+    rec[3] = (f1 - b1) | ((f2 - b2) << 32);
+    return (uint32_t)(f0 - b0);
+  }
+  __device__ static bool visit_rec(const GraphView &g, const uint64_t *rec, uint32_t i,
+                                   uint32_t *o) {
+    const uint64_t b0 = rec[0], b1 = rec[1], b2 = rec[2], ln = rec[3];
+    const uint64_t f1 = b1 + (uint32_t)ln, f2 = b2 + (ln >> 32);
+    const uint64_t p0 = b0 + i;
+    const uint32_t x = g.wc[p0];
+    if (b1 == f1 || b2 == f2) return false;   // never: each holds R's third vertex
+    uint64_t p1, p2;
+    find2_u32<uint64_t>(g.wc, b1, f1, b2, f2, x, p1, p2);
+    if (p1 == f1 || p2 == f2) return false;
+    o[0] = g.wt[p0];
+    o[1] = g.wt[p1];
+    o[2] = g.wt[p2];
+    return true;
+  }
   __device__ static uint32_t len(const GraphView &g, uint32_t R) {
     const uint32_t e0 = g.te[3ull * R], e1 = g.te[3ull * R + 1], e2 = g.te[3ull * R + 2];
     uint64_t s0 = g.wp[e0 + 1] - g.wp[e0], s1 = g.wp[e1 + 1] - g.wp[e1],
@@ -954,7 +1003,8 @@ __global__ void __launch_bounds__(kPeelBlock, kLink ? 4 : 5) k_peel(PeelArgs a) 
         a.round[R] = t;
         a.pst[R] = kPeeledNow;
         a.cnt[R] = k;
-        w = Sh::len(g, R);
+        if constexpr (RecOf<Sh>::value) w = Sh::len_rec(g, R, &a.frec[4 * i]);
+        else w = Sh::len(g, R);
       }
       // block-wide inclusive scan of w
       uint32_t incl = wave_incl_scan(w);
@@ -1028,6 +1078,7 @@ __global__ void __launch_bounds__(kPeelBlock, kLink ? 4 : 5) k_peel(PeelArgs a) 
         lpair[j] = ~0ull;
       }
       uint32_t R = 0, idx = 0;
+      uint64_t slot = 0;   // R's frontier slot
       bool have = false;
       if (p < P && use_map) {
         // the slot holding p lies between the slots of p's chunk and of the
@@ -1045,6 +1096,7 @@ __global__ void __launch_bounds__(kPeelBlock, kLink ? 4 : 5) k_peel(PeelArgs a) 
           else hi = mid;
         }
         R = F[lo];
+        slot = lo;
         idx = (uint32_t)(p - start(lo));
       } else if (p < P) {
         // block segment holding unit p (s_boff[lo] <= p < s_boff[hi]): a
@@ -1080,11 +1132,15 @@ __global__ void __launch_bounds__(kPeelBlock, kLink ? 4 : 5) k_peel(PeelArgs a) 
           }
         }
         R = F[x0];
+        slot = x0;
         const uint64_t before = (x0 > b0) ? a.wscan[x0 - 1] : 0;
         idx = (uint32_t)(qoff - before);
       }
       have = p < P;
-      if (have && Sh::visit(g, R, idx, others)) {
+      bool hit = false;
+      if constexpr (RecOf<Sh>::value) hit = have && Sh::visit_rec(g, &a.frec[4 * slot], idx, others);
+      else hit = have && Sh::visit(g, R, idx, others);
+      if (hit) {
         visits++;
         uint32_t rr[NO];   // peel states
         bool dead = false, lead = true;
