@@ -118,30 +118,44 @@ __device__ __forceinline__ IdxT find_u32(const uint32_t *a, IdxT lo, IdxT hi, ui
   return (p < hi && a[p] == x) ? p : hi;
 }
 
-// Indices of x in two non-empty sorted ranges a[lo1, hi1) and a[lo2, hi2)
-// (hi of a range when x is absent from it). The two searches advance in
-// lockstep, so their chains of dependent loads overlap; a range already
-// narrowed down keeps loading its last valid slot, so every load is in bounds.
+// Indices of x in two non-empty, strictly increasing ranges a[lo1, hi1) and
+// a[lo2, hi2) (hi of a range when x is absent from it). The two searches
+// advance in lockstep, so their chains of dependent loads overlap; a range
+// already settled keeps loading its last valid slot, so every load is in
+// bounds. A present x is always tested as a midpoint (the step that brings a
+// range's upper end down to x's slot tests that slot), so a range is settled
+// as soon as its midpoint equals x, and no load follows the search.
 template <typename IdxT>
 __device__ __forceinline__ void find2_u32(const uint32_t *a, IdxT lo1, IdxT hi1, IdxT lo2,
                                           IdxT hi2, uint32_t x, IdxT &p1, IdxT &p2) {
   IdxT l1 = lo1, h1 = hi1, l2 = lo2, h2 = hi2;
+  p1 = hi1;
+  p2 = hi2;
   while (l1 < h1 || l2 < h2) {
     const IdxT m1 = l1 < h1 ? l1 + ((h1 - l1) >> 1) : hi1 - 1;
     const IdxT m2 = l2 < h2 ? l2 + ((h2 - l2) >> 1) : hi2 - 1;
     const uint32_t v1 = a[m1], v2 = a[m2];
     if (l1 < h1) {
-      if (v1 < x) l1 = m1 + 1;
-      else h1 = m1;
+      if (v1 == x) {
+        p1 = m1;
+        h1 = l1;
+      } else if (v1 < x) {
+        l1 = m1 + 1;
+      } else {
+        h1 = m1;
+      }
     }
     if (l2 < h2) {
-      if (v2 < x) l2 = m2 + 1;
-      else h2 = m2;
+      if (v2 == x) {
+        p2 = m2;
+        h2 = l2;
+      } else if (v2 < x) {
+        l2 = m2 + 1;
+      } else {
+        h2 = m2;
+      }
     }
   }
-  const uint32_t y1 = a[l1 < hi1 ? l1 : hi1 - 1], y2 = a[l2 < hi2 ? l2 : hi2 - 1];
-  p1 = (l1 < hi1 && y1 == x) ? l1 : hi1;
-  p2 = (l2 < hi2 && y2 == x) ? l2 : hi2;
 }
 
 // Last index i in [0, n) with a[i] <= x for a non-decreasing u64 array whose
