@@ -408,7 +408,7 @@ enum BufId : int {
   B_THR,   // approximate decomposition: bucket ends
   B_C2G,   // 4-clique counting: global C2 slices for rows above the LDS cap
   B_CSLOT, // peel: chunk -> frontier slot map of a large round
-  B_FREC,  // peel, (3,4): per frontier slot, the list ranges its visits search
+  B_FREC,  // peel, (2,3) and (3,4): per frontier slot, the list ranges its visits search
   // s = 5..7 (nd_gen.hip): clique levels, sorted tuples, r-clique table,
   // s-clique members and the incidence CSR
   B_GEN_L0, B_GEN_L1, B_GEN_CNT, B_GEN_OFF, B_GEN_RTUP, B_GEN_STUP, B_GEN_RCL, B_GEN_SM,

@@ -16,7 +16,8 @@ nd_status nd_stage_peel(nd_ctx *c, const GraphView &g) {
   if (!(pa.pst = (uint8_t *)nd_buf(c, B_PSTATE, nr, &st))) return st;
   if (!(pa.uf = (uint32_t *)nd_buf(c, B_UF, nr * 4, &st))) return st;
   if (!(pa.L = (uint32_t *)nd_buf(c, B_L, nr * 4, &st))) return st;
-  if (c->r == 3 && c->s == 4 && !(pa.frec = (uint64_t *)nd_buf(c, B_FREC, nr * 32, &st)))
+  if (((c->r == 3 && c->s == 4) || (c->r == 2 && c->s == 3)) &&
+      !(pa.frec = (uint64_t *)nd_buf(c, B_FREC, nr * 32, &st)))
     return st;
   if (!(pa.F0 = (uint32_t *)nd_buf(c, B_F0, nr * 4, &st))) return st;
   if (!(pa.F1 = (uint32_t *)nd_buf(c, B_F1, nr * 4, &st))) return st;

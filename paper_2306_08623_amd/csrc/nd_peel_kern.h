@@ -53,7 +53,7 @@ struct PeelArgs {
   uint8_t *pst;       // peel state: kAlive, kPeeledNow (this round), kPeeledBefore
   uint32_t *uf;       // union-find parent
   uint32_t *L;        // nearest lower core link of a uf root
-  uint64_t *frec;     // (3,4): per frontier slot, 32 B of list ranges (Shape::len_rec)
+  uint64_t *frec;     // (2,3), (3,4): per frontier slot, 32 B of list ranges (Shape::len_rec)
   uint32_t *F0, *F1;  // frontiers by round parity
   uint64_t *wscan;    // per frontier slot: inclusive work prefix in its segment
   uint32_t *al0, *al1;  // remaining r-cliques by scan parity, one segment per block
@@ -438,6 +438,32 @@ struct Shape<1, 2> {
 template <>
 struct Shape<2, 3> {
   static constexpr int kOthers = 2;
+  static constexpr bool kRec = true;
+  // record: the CSR start of the endpoint with the shorter list (probed),
+  // the start and length of the other one's list
+  __device__ static uint32_t len_rec(const GraphView &g, uint32_t R, uint64_t *rec) {
+    const uint32_t u = g.eu[R], v = g.ev[R];
+    uint64_t bp = g.rp[u], ep = g.rp[u + 1], bq = g.rp[v], eq = g.rp[v + 1];
+    // the same choice of the probed endpoint as visit() below
+    if (eq - bq < ep - bp) {
+      uint64_t t = bp; bp = bq; bq = t;
+      t = ep; ep = eq; eq = t;
+    }
+    rec[0] = bp;
+    rec[1] = bq;
+    rec[2] = eq - bq;
+    return (uint32_t)(ep - bp);
+  }
+  __device__ static bool visit_rec(const GraphView &g, const uint64_t *rec, uint32_t i,
+                                   uint32_t *o) {
+    const uint64_t sp = rec[0] + i, bq = rec[1], eq = rec[1] + rec[2];
+    const uint32_t x = g.col[sp];
+    const uint64_t sq = find_u32<uint64_t>(g.col, bq, eq, x);
+    if (sq == eq) return false;
+    o[0] = g.eid[sp];
+    o[1] = g.eid[sq];
+    return true;
+  }
   __device__ static uint32_t len(const GraphView &g, uint32_t R) {
     const uint32_t u = g.eu[R], v = g.ev[R];
     const uint64_t du = g.rp[u + 1] - g.rp[u], dv = g.rp[v + 1] - g.rp[v];

@@ -101,6 +101,7 @@ void estimate(uint32_t n, uint64_t nnz, const uint64_t *rp, const uint32_t *col,
   if (s >= 3) w += 24ull * (m + 1) + 36ull * tri;
   if (r == 2 && s == 4) w += 48ull * tri;   // probe parts, lengths, running sums
   if (r == 3 && s == 4) w += 32ull * tri;   // the peel's per-frontier-slot list ranges
+  if (r == 2 && s == 3) w += 32ull * m;     // the same for (2,3)
   if (r == 1 && s >= 3) w += 24ull * (m + 1);   // per-slot triangle counts and sums
   if (r == 1 && s == 4) w += 48ull * tri;       // per-triangle-probe parts and sums
   if (ws) *ws = w;
